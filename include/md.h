@@ -1,0 +1,252 @@
+/*
+ * md.h -- C ABI of the MI355X (gfx950) soft-sphere molecular-dynamics hot path.
+ *
+ * Method: D. C. Rapaport, "Enhanced molecular dynamics performance with a
+ * programmable graphics processor" (arXiv:0911.5631).  The library advances
+ * atoms interacting through the soft-sphere potential -- Eq. (1), the
+ * Lennard-Jones form, truncated at r_c = 2^(1/6) with the constant epsilon
+ * added so that u(r_c) = 0 (Sec. 2.1) -- in a periodic cube centred at the
+ * origin, in reduced units sigma = epsilon = m = 1.
+ *
+ * The path per time step (Sec. 2.1, loop steps (a)-(e)):
+ *   (a) half-step velocity update and full-step position update (leapfrog);
+ *   (b) when a rebuild is due: periodic wrap, cell binning (cell assignment,
+ *       layer assignment, cell-order reordering: Secs. 2.4-2.5) and the
+ *       neighbour-matrix build over 27 cells without Newton's third law
+ *       (Secs. 2.3-2.4);
+ *   (c) forces and potential energy from the neighbour matrix (Sec. 2.4);
+ *   (d) second half-step velocity update;
+ *   (e) kinetic energy, maximum speed and the rebuild decision: the list is
+ *       rebuilt when the accumulated sum of vmax*dt exceeds delta/2
+ *       (Sec. 2.1).
+ * With shell == 0 the library runs the plain cell method instead (Sec. 2.1):
+ * every step re-bins and evaluates forces straight from the 27 neighbouring
+ * cells, with no stored list.
+ *
+ * Conventions shared by every entry point:
+ *   - Host arrays of per-atom vectors are row-major double[n][3] in the
+ *     caller's ORIGINAL atom order; the library keeps its own storage order
+ *     (cell order) on the device and translates.
+ *   - Ownership: the library copies host inputs and owns all device memory,
+ *     which it obtains through the caller's md_allocator (NULL: hipMalloc /
+ *     hipFree).  Host buffers passed in are never retained.
+ *   - Streams: every device operation of a system is enqueued on the HIP
+ *     stream given at creation (NULL: the null stream).  Calls marked
+ *     "async" return before the device work completes; calls marked
+ *     "sync" synchronise that stream first.
+ *   - Errors found on the device (neighbour-matrix or cell-layer overflow,
+ *     an escaped atom, a non-finite coordinate) are latched in the system,
+ *     stop all further device work on it, and are returned by the next
+ *     synchronising call.  Neighbour-matrix and cell-layer overflows are
+ *     repaired inside md_step / md_forces / md_build_nebr by enlarging the
+ *     capacity and redoing the interrupted work; they surface as errors only
+ *     if the larger allocation fails.  MD_ERR_HIP is sticky: after it only
+ *     md_destroy / md_batch_destroy is valid.
+ *   - Threading: one host thread at a time per md_system / md_batch.
+ */
+#ifndef PAPER_0911_5631_AMD_MD_H
+#define PAPER_0911_5631_AMD_MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct md_system md_system; /* one periodic system (opaque) */
+typedef struct md_batch md_batch;   /* many independent systems stepped together (opaque) */
+
+typedef enum {
+    MD_OK = 0,
+    MD_ERR_INVALID_ARG = -1,   /* a NULL pointer, n <= 0, box/dt <= 0, bad enum, ... */
+    MD_ERR_BOX_TOO_SMALL = -2, /* fewer than 3 cells per edge (G = floor(L / r_n) < 3) */
+    MD_ERR_OOM = -3,           /* the allocator returned NULL */
+    MD_ERR_HIP = -4,           /* a HIP runtime call failed (sticky) */
+    MD_ERR_NEBR_OVERFLOW = -5, /* neighbour matrix could not be enlarged */
+    MD_ERR_ATOM_ESCAPED = -6,  /* a coordinate left [-3L/2, 3L/2) before a wrap */
+    MD_ERR_NONFINITE = -7,     /* a coordinate became NaN or infinite */
+    MD_ERR_STATE = -8,         /* call not valid in the current state */
+    MD_ERR_NO_SLOT = -9,       /* batch: no free slot */
+    MD_ERR_CELL_OVERFLOW = -10 /* cell-layer matrix could not be enlarged */
+} md_status;
+
+/* Arithmetic of the pair forces.  Positions and velocities are always FP64. */
+typedef enum {
+    MD_FORCE_FP32 = 0, /* FP64 separations and cutoff tests, FP32 pair forces,
+                          compensated FP32 sums of energy and virial */
+    MD_FORCE_FP64 = 1  /* everything in FP64 */
+} md_precision;
+
+/* md_params.flags */
+#define MD_EVEN_CELLS 1u /* round G down to even (the rule behind the paper's
+                            cell counts in Tables 1 and 5); default floor(L / r_n) */
+
+typedef struct {
+    int64_t n_atoms;   /* N >= 1 and N < 2^26 */
+    double box;        /* edge L of the cube [-L/2, L/2)^3 */
+    double r_cut;      /* interaction cutoff r_c; 2^(1/6) selects the soft sphere
+                          (shift +1 so u(r_c) = 0); any other value is plain
+                          truncated Lennard-Jones (no shift) */
+    double shell;      /* neighbour shell delta (r_n = r_c + delta); 0 selects
+                          the cell-list-only method (re-bin every step) */
+    double dt;         /* time step */
+    int32_t precision; /* md_precision */
+    int32_t nebr_cap;  /* initial per-atom neighbour capacity; 0 = 48 */
+    int32_t cell_cap;  /* initial per-cell layer capacity; 0 = 16 */
+    uint32_t flags;    /* MD_EVEN_CELLS */
+} md_params;
+
+typedef struct {
+    double ke;              /* kinetic energy  (1/2) sum v^2 */
+    double pe;              /* potential energy, sum over pairs of u(r) */
+    double virial;          /* sum over pairs of r . F_pair = f(r) r^2 */
+    double ke_per_atom, pe_per_atom, virial_per_atom;
+    double vmax;            /* max |v| */
+    double disp;            /* accumulated vmax*dt since the last rebuild */
+    int64_t n_pairs;        /* unordered pairs in the neighbour matrix (0 in cell-list-only mode) */
+    int64_t n_rebuilds;     /* rebuilds performed by md_step (not counting creation) */
+    int64_t step;           /* completed time steps */
+    int32_t max_nebr;       /* largest per-atom list length at the last build */
+    int32_t max_cell;       /* largest cell occupancy at the last binning */
+    int32_t rebuild_due;    /* 1 if the next step starts with a rebuild */
+    int32_t cells_per_edge; /* G */
+} md_props_t;
+
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx); /* device memory, >= 256-byte aligned */
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} md_allocator;
+
+/* Text for a status code (static storage). */
+const char *md_status_string(md_status s);
+
+/* Cells per edge G for these parameters (floor(L / r_n), or its even floor
+ * with MD_EVEN_CELLS), without creating anything.  Sec. 2.1 defines G. */
+md_status md_cells_per_edge(const md_params *p, int32_t *G);
+
+/* Device bytes md_create would allocate for these parameters (for admission
+ * against a memory budget).  Sync-free. */
+md_status md_query_bytes(const md_params *p, size_t *bytes);
+
+/* Create a system from host positions and velocities (n x 3 doubles each,
+ * any order, positions anywhere in [-3L/2, 3L/2)) and evaluate step 0: wrap,
+ * bin, build the neighbour matrix (unless shell == 0), forces, properties,
+ * and the first rebuild decision (accumulated displacement = vmax*dt).
+ * hip_stream: a hipStream_t, or NULL.  a: allocator, or NULL for hipMalloc.
+ * On success *out owns a new system.  Async (the initial copies are staged
+ * through host memory owned by the library). */
+md_status md_create(const md_params *p, const double *pos, const double *vel,
+                    const md_allocator *a, void *hip_stream, md_system **out);
+
+/* Periodic wrap, cell assignment and stable cell-order reordering (cell
+ * assignment Sec. 2.2/Code "CellAtomAssign", layer assignment Sec. 2.4,
+ * reordering Sec. 2.5): atoms end up stored cell by cell, and within a cell in
+ * their previous storage order.  Marks the neighbour matrix stale.  Async. */
+md_status md_bin_cells(md_system *s);
+
+/* Build the neighbour matrix W[m][i] (Sec. 2.4): for every atom, all atoms
+ * j != i of the 27 surrounding cells with r^2 < r_n^2, visited cell by cell
+ * (offsets z-major, x fastest) and in storage order within a cell.  Requires
+ * current bins (call md_bin_cells first after md_set_state).  Not available
+ * in cell-list-only mode (MD_ERR_STATE).  Async. */
+md_status md_build_nebr(md_system *s);
+
+/* Forces, per-atom energies and virials at the current positions (Sec. 2.4
+ * force algorithm; cell method when shell == 0), plus the properties.
+ * Stores the forces used by the next md_step.  Async. */
+md_status md_forces(md_system *s);
+
+/* Advance n_steps leapfrog steps (a)-(e), rebuilding on the device whenever
+ * the displacement rule fires.  Work is replayed from captured HIP graphs.
+ * Async. */
+md_status md_step(md_system *s, int64_t n_steps);
+
+/* Properties after the last completed step (or creation / md_forces).
+ * Sync; returns latched device errors. */
+md_status md_props(md_system *s, md_props_t *out);
+
+/* Copy out positions, velocities and forces (each may be NULL; n x 3
+ * doubles, original atom order) and the completed step count.  Sync. */
+md_status md_get_state(md_system *s, double *pos, double *vel, double *force, int64_t *step);
+
+/* Per-atom pair-energy and virial sums (each pair counted on both of its
+ * atoms, so the sums are 2 PE and 2 W) from the last force evaluation, in
+ * original order; either may be NULL.  Sync. */
+md_status md_get_atom_energies(md_system *s, double *u_atom, double *w_atom);
+
+/* Replace positions and velocities (n x 3, original order).  Marks bins and
+ * the neighbour matrix stale; the next md_forces / md_step re-bins, rebuilds
+ * and re-evaluates forces before integrating.  Async. */
+md_status md_set_state(md_system *s, const double *pos, const double *vel);
+
+/* Scalar cell index (c_z*G + c_y)*G + c_x of every atom at the last
+ * binning, original order.  Sync. */
+md_status md_get_cells(md_system *s, int32_t *cell_of_atom);
+
+/* Storage order after the last binning: order[p] = original index of the
+ * atom stored at position p; cell_start[c] = first position of cell c,
+ * cell_start[G^3] = n (either may be NULL).  Sync. */
+md_status md_get_bins(md_system *s, int32_t *order, int32_t *cell_start);
+
+/* Neighbour-matrix entries as ordered pairs (i, j) of original indices, i
+ * != j; each unordered pair appears twice (once from each side).  Stores at
+ * most cap pairs, *n gets the total.  Sync. */
+md_status md_get_pairs(md_system *s, int64_t cap, int32_t *i, int32_t *j, int64_t *n);
+
+/* Bracket the launches of the force kernel with HIP events from now on
+ * (enable != 0), or stop.  md_kernel_time reports launches and the summed
+ * event-measured duration since the last enable.  Sync. */
+md_status md_profile(md_system *s, int32_t enable);
+md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms);
+
+/* Release the system and its device memory (synchronises its stream). */
+void md_destroy(md_system *s);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent systems advanced together.  Each kernel launch
+ * of a batched step covers the tiles of every active system, so small
+ * systems share the GPU; the per-system arithmetic is exactly that of an
+ * md_system with the same parameters, so a system's trajectory is the same
+ * bit for bit alone or in any mix.
+ * ------------------------------------------------------------------------- */
+
+/* A batch with room for max_slots systems and hbm_budget bytes of their
+ * device state; steps_per_run steps are replayed per md_batch_run. */
+md_status md_batch_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_run,
+                          const md_allocator *a, void *hip_stream, md_batch **out);
+
+/* Admit a system that is to advance n_steps steps; evaluates its step 0
+ * (as md_create).  MD_ERR_OOM if it does not fit the remaining budget,
+ * MD_ERR_NO_SLOT if every slot is busy; the caller retries later.  Async. */
+md_status md_batch_admit(md_batch *b, const md_params *p, const double *pos, const double *vel,
+                         int64_t n_steps, int32_t *slot);
+
+/* Advance every admitted, unfinished system by up to steps_per_run steps.
+ * Async. */
+md_status md_batch_run(md_batch *b);
+
+/* Slots whose systems have completed all their steps and are not yet
+ * released: writes up to cap slot numbers, *n_done gets the count.  Sync. */
+md_status md_batch_poll(md_batch *b, int32_t *done, int32_t cap, int32_t *n_done);
+
+/* Properties / state of the system in a slot (as md_props / md_get_state).
+ * Sync. */
+md_status md_batch_props(md_batch *b, int32_t slot, md_props_t *out);
+md_status md_batch_get_state(md_batch *b, int32_t slot, double *pos, double *vel, int64_t *step);
+
+/* Free a slot and its device memory.  Sync. */
+md_status md_batch_release(md_batch *b, int32_t slot);
+
+/* Bytes of the budget in use, and admitted systems. */
+md_status md_batch_usage(md_batch *b, size_t *bytes, int32_t *n_systems);
+
+/* Release the batch and every admitted system. */
+void md_batch_destroy(md_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_0911_5631_AMD_MD_H */

@@ -1,0 +1,114 @@
+// md_device.h -- data layout shared by the gfx950 kernels and the host engine.
+//
+// Every system ("replica") owns its own device buffers; kernels find them
+// through a per-replica descriptor (SlotDev) and keep per-replica mutable
+// state in a control block (CtlDev).  A launch covers the tiles of all
+// replicas of an engine (tile -> replica via a table), so one kernel launch
+// advances many systems and a single system is an engine with one replica.
+//
+// Step numbering: step k (k >= 1) of a replica is the k-th leapfrog step
+// after creation; "state k" is r(k), v(k).  Storage of the time levels:
+//   r(k)      in P[k & 1]
+//   v(k-1/2)  in V[k & 1]   (during a run)
+//   v(k)      in V[(k+1) & 1] when the replica is clean at step k
+// The cell-layer matrix comes in three sets; the rows of state k live in set
+// k % 3, so one step can read its rows while the next step's rows are
+// written and the set after that is cleared.
+#pragma once
+
+#include <stdint.h>
+
+namespace md {
+
+constexpr int TILE = 256;          // atoms per tile (one workgroup of 4 wave64)
+constexpr int CTILE = 2048;        // cells per scan tile (8 per thread)
+constexpr int J_BITS = 26;         // neighbour entry: index in the low 26 bits
+constexpr int32_t J_MASK = (1 << J_BITS) - 1;
+constexpr int NPART = 8;           // doubles per tile in the property partials
+constexpr int MAX_GRID = 2048;     // persistent-style grid bound (256 CUs x 8)
+constexpr int OVF_CAP = 4096;      // per-set overflow list of cell-layer rows
+constexpr int VSPREAD = 32;        // slots of each max-speed ring entry (one per 128-byte line)
+
+// Latched error bits (CtlDev::err).
+enum : int32_t {
+  ERR_CELL = 2,       // a cell-layer set overflowed beyond its overflow list (repairable)
+  ERR_ESCAPED = 4,    // a coordinate outside [-3L/2, 3L/2) when binned
+  ERR_NONFINITE = 8,  // NaN / Inf coordinate
+  ERR_SCAN = 16,      // scan look-back gave up (safety net)
+};
+
+// Modes of the step kernel.
+enum : int32_t {
+  MODE_STEP = 0,    // forces (c) + (d) + (e) [+ (a) of the next step and its binning]
+  MODE_FORCES = 1,  // force evaluation at a clean state: store F, u_i, w_i, partials
+  MODE_BUILD = 2,   // neighbour matrix only, at a clean state
+};
+
+// Per-replica device descriptor: read-only while kernels run (the host swaps
+// the *_alt buffers after a reordering and uploads the descriptor again).
+struct SlotDev {
+  double *P[2][3];                  // positions x, y, z; two time-level buffers
+  double *V[2][3];                  // velocities; two time-level buffers
+  int32_t *id, *id_alt;             // original atom index of each storage position
+  void *F, *F_alt;                  // forces, SoA [3][npad] of float or double
+  void *UA, *UA_alt;                // per-atom u then w, [2][npad] of float or double
+  int32_t *cell, *cell_alt;         // cell of each atom at its latest binning
+  int32_t *m, *m_alt;               // neighbour-list length per atom
+  int32_t *W, *W_alt;               // neighbour matrix [mcap][npad]
+  int32_t *cnt[3];                  // per set: occupancy of every cell
+  int32_t *H[3];                    // per set: cell-layer rows [ncell][hcap]
+  int32_t *ovf[3];                  // per set: (cell, atom) pairs beyond hcap
+  int32_t *ovf_n;                   // [3] fill of the overflow lists
+  int32_t *cs;                      // cell_start[ncell + 1] of the last reordering scan
+  int32_t *perm;                    // reordering: old index of new position p
+  int32_t *inv;                     // reordering: new position of old index a
+  unsigned long long *scan_st;      // scan look-back status per cell tile
+  double *part;                     // per-tile partial properties [ntiles][NPART]
+  unsigned long long *vring;        // max v^2 of step k: [k % 3][VSPREAD] slots, 16 words apart
+  double L, halfL, invW, rn2, rc2, dt, hdt, half_shell, ushift, pad0;
+  int32_t n, G, ncell, hcap, mcap, npad;
+  int32_t ntiles;    // atom tiles: ceil(n / TILE)
+  int32_t nctiles;   // cell tiles: ceil((ncell + 1) / CTILE), so one holds cell_start[ncell]
+  int32_t tile_off, ctile_off;
+  int32_t cpt;       // cells cleared per atom tile: ceil(ncell / ntiles)
+  int32_t fp64, cell_only, pad1;
+};
+
+// Per-replica mutable control block.  Written by the host between launches,
+// by single-workgroup kernels, or by one designated thread of the step kernel
+// (fields nobody else reads in that launch).
+struct CtlDev {
+  int64_t done;        // steps completed
+  int64_t target;      // steps to reach
+  int64_t base;        // `done` when the current graph replay started
+  int64_t force_step;  // step whose binning is a rebuild regardless of the rule
+  int64_t err_step;    // first step that could not be evaluated
+  int64_t n_rebuilds;  // rebuilds by the displacement rule
+  uint64_t vmax_ring[3];  // max v(k)^2 of ring entry k % 3, gathered by k_props (host view)
+  double disp_ring[3];    // accumulated displacement after step k, slot k % 3
+  int32_t clean;       // 1: r(done), v(done), F(done) are held; 0: drifted to r(done+1)
+  int32_t variant;     // which of the two descriptors of the replica is current
+  int32_t err;         // latched ERR_* bits
+  int32_t max_h;       // largest cell occupancy seen by a reordering scan
+  // properties reduced by k_props
+  double ke, pe, vir, vmax2;
+  int64_t sum_m;
+  int32_t max_m, pad0;
+};
+
+// Engine-wide header (device int32[8]).
+enum { HDR_NTILES = 0, HDR_NCTILES = 1, HDR_TICKET = 2 };
+
+// Each replica has two descriptors: the second swaps every double-buffered
+// array (the positions/velocities buffer pair and each array with its _alt).
+// A reordering gathers into the other buffers and flips CtlDev::variant.
+struct Tables {
+  const SlotDev *slots;       // [2 * nslots]: descriptor variant v of replica r at 2 r + v
+  CtlDev *ctl;
+  const int32_t *tile_rep;    // atom tile -> replica
+  const int32_t *ctile_rep;   // cell tile -> replica
+  int32_t *hdr;
+  int32_t nslots;
+};
+
+}  // namespace md

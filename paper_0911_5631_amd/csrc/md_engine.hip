@@ -1,0 +1,1319 @@
+// md_engine.hip -- host side of the C ABI declared in include/md.h.
+//
+// An Engine owns a HIP stream, the per-replica descriptors and control
+// blocks, and the tile tables every kernel walks.  md_system is an engine
+// with one replica; md_batch is an engine with many slots.
+//
+// Steps are replayed from captured HIP graphs of K steps (K a power of two up
+// to 64): K launches of the step kernel and one counter update.  Graph
+// boundaries fall on multiples of 64 in each replica's step count, and at
+// those boundaries the replicas that are mid-run are reordered into cell
+// order (a relabeling that leaves every force sum unchanged).  All kernel
+// arguments are pointers to device tables, so graphs stay valid when slots
+// are admitted or released.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "md.h"
+#include "md_device.h"
+#include "md_kernels.h"
+
+using namespace md;
+
+namespace {
+
+constexpr int DEFAULT_MCAP = 48;
+constexpr int DEFAULT_HCAP = 16;
+constexpr int GRAPH_CHUNK = 64;      // steps per replay graph; reordering period
+constexpr int PROFILE_SETS = 2;      // ping-pong event sets when profiling
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Geometry {
+  int64_t n;
+  int G, ncell, ntiles, nctiles, npad, hcap, mcap, cpt;
+  bool cell_only, fp64;
+  double L, rc, shell, rn;
+};
+
+md_status geometry(const md_params *p, Geometry *g) {
+  if (!p || !g) return MD_ERR_INVALID_ARG;
+  if (p->n_atoms <= 0 || p->n_atoms >= (int64_t(1) << J_BITS)) return MD_ERR_INVALID_ARG;
+  if (!(p->box > 0) || !(p->dt > 0) || !(p->r_cut > 0) || !(p->shell >= 0))
+    return MD_ERR_INVALID_ARG;
+  if (!std::isfinite(p->box) || !std::isfinite(p->dt) || !std::isfinite(p->r_cut) ||
+      !std::isfinite(p->shell))
+    return MD_ERR_INVALID_ARG;
+  if (p->precision != MD_FORCE_FP32 && p->precision != MD_FORCE_FP64) return MD_ERR_INVALID_ARG;
+  if (p->nebr_cap < 0 || p->cell_cap < 0 || (p->flags & ~MD_EVEN_CELLS)) return MD_ERR_INVALID_ARG;
+  g->n = p->n_atoms;
+  g->L = p->box;
+  g->rc = p->r_cut;
+  g->shell = p->shell;
+  g->rn = p->r_cut + p->shell;
+  g->cell_only = p->shell == 0.0;
+  g->fp64 = p->precision == MD_FORCE_FP64;
+  const double q = std::floor(g->L / g->rn);
+  if (q < 3) return MD_ERR_BOX_TOO_SMALL;
+  if (q > 1290) return MD_ERR_INVALID_ARG;  // G^3 must fit int32 cell indices
+  int G = (int)q;
+  if (p->flags & MD_EVEN_CELLS) G -= (G & 1);
+  if (G < 3) return MD_ERR_BOX_TOO_SMALL;
+  g->G = G;
+  g->ncell = G * G * G;
+  g->ntiles = (int)((g->n + TILE - 1) / TILE);
+  g->nctiles = (g->ncell + 1 + CTILE - 1) / CTILE;
+  g->npad = g->ntiles * TILE;
+  g->cpt = (g->ncell + g->ntiles - 1) / g->ntiles;
+  g->hcap = p->cell_cap > 0 ? p->cell_cap : DEFAULT_HCAP;
+  g->mcap = g->cell_only ? 0 : (p->nebr_cap > 0 ? p->nebr_cap : DEFAULT_MCAP);
+  return MD_OK;
+}
+
+// Layout of the per-replica state block (everything but H and W), in order.
+struct Layout {
+  size_t pv, ids, fu, cellm, perm, cnt, cs, ovf, scan, part, vring, total;
+};
+Layout layout(const Geometry &g) {
+  const size_t R = g.fp64 ? 8 : 4, np = g.npad;
+  const size_t cells = (size_t)g.nctiles * CTILE;
+  Layout l{};
+  size_t b = 0;
+  l.pv = b;
+  b += round_up(12 * np * 8, 256);          // P[2][3], V[2][3]
+  l.ids = b;
+  b += round_up(2 * np * 4, 256);           // id, id_alt
+  l.fu = b;
+  b += round_up(10 * np * R, 256);          // F, F_alt, UA, UA_alt
+  l.cellm = b;
+  b += round_up(4 * np * 4, 256);           // cell, cell_alt, m, m_alt
+  l.perm = b;
+  b += round_up(2 * np * 4, 256);           // perm, inv
+  l.cnt = b;
+  b += 3 * round_up(cells * 4, 256);        // cnt[3]
+  l.cs = b;
+  b += round_up(cells * 4, 256);            // cell_start
+  l.ovf = b;
+  b += round_up(3 * 2 * OVF_CAP * 4 + 3 * 4, 256);  // ovf[3], ovf_n[3]
+  l.scan = b;
+  b += round_up((size_t)g.nctiles * 8, 256);
+  l.part = b;
+  b += round_up((size_t)g.ntiles * NPART * 8, 256);
+  l.vring = b;
+  b += round_up((size_t)3 * VSPREAD * 16 * 8, 256);
+  l.total = b;
+  return l;
+}
+size_t h_bytes(const Geometry &g, int hcap) {
+  return 3 * round_up((size_t)g.ncell * hcap * 4, 256);
+}
+size_t w_bytes(const Geometry &g, int mcap) { return 2 * round_up((size_t)mcap * g.npad * 4, 256); }
+size_t total_bytes(const Geometry &g) {
+  return layout(g).total + h_bytes(g, g.hcap) + (g.mcap ? w_bytes(g, g.mcap) : 0);
+}
+
+struct Replica {
+  md_params p{};
+  Geometry g{};
+  SlotDev dev[2]{};   // descriptor variants
+  void *state = nullptr, *hmat = nullptr, *wmat = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct Engine {
+  hipStream_t user = nullptr;
+  hipStream_t work = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  md_allocator alloc{};
+  bool custom_alloc = false;
+  int max_slots = 0;
+  bool batch = false;
+  std::vector<Replica *> rep;
+  SlotDev *d_slots = nullptr;   // [2 * max_slots]
+  CtlDev *d_ctl = nullptr;
+  int32_t *d_tile_rep = nullptr, *d_ctile_rep = nullptr, *d_hdr = nullptr;
+  int tile_cap = 0, ctile_cap = 0;
+  CtlDev *h_ctl = nullptr;      // pinned
+  SlotDev *h_slots = nullptr;   // pinned [2 * max_slots]
+  int32_t *h_tab = nullptr;     // pinned: hdr + tile tables
+  size_t h_tab_cap = 0;
+  int grid = 1, cgrid = 1;
+  std::map<int, hipGraphExec_t> graphs;
+  bool sticky_hip = false;
+  bool verbose = getenv("MD_VERBOSE") != nullptr;
+  size_t budget = 0, used = 0;
+  int steps_per_run = GRAPH_CHUNK;
+  unsigned scan_epoch = 1;
+  int64_t host_target = 0;      // single system: target of the last md_step
+  // profiling of the step kernel (eager launches bracketed by events: events
+  // recorded by graph nodes cannot be timed with hipEventElapsedTime)
+  bool profiling = false;
+  hipEvent_t prof_ev[PROFILE_SETS][GRAPH_CHUNK][2]{};
+  int prof_pending[PROFILE_SETS] = {0, 0};
+  int prof_next = 0;
+  long long prof_launches = 0;
+  double prof_ms = 0.0;
+
+  Tables tables() const {
+    Tables t;
+    t.slots = d_slots;
+    t.ctl = d_ctl;
+    t.tile_rep = d_tile_rep;
+    t.ctile_rep = d_ctile_rep;
+    t.hdr = d_hdr;
+    t.nslots = max_slots;
+    return t;
+  }
+
+  void *dmalloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (custom_alloc) {
+      p = alloc.alloc(bytes, alloc.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    return p;
+  }
+  void dfree(void *p) {
+    if (!p) return;
+    if (custom_alloc)
+      alloc.free(p, alloc.ctx);
+    else
+      (void)hipFree(p);
+  }
+  md_status fail(const char *where = nullptr, hipError_t err = hipSuccess) {
+    sticky_hip = true;
+    if (verbose)
+      fprintf(stderr, "md: HIP failure%s%s%s%s\n", where ? " in " : "", where ? where : "",
+              err != hipSuccess ? ": " : "", err != hipSuccess ? hipGetErrorString(err) : "");
+    return MD_ERR_HIP;
+  }
+  md_status check(const char *where) {
+    hipError_t err = hipGetLastError();
+    return err == hipSuccess ? MD_OK : fail(where, err);
+  }
+  md_status enter() {
+    if (sticky_hip) return MD_ERR_HIP;
+    hipError_t err = hipEventRecord(ev_in, user);
+    if (err == hipSuccess) err = hipStreamWaitEvent(work, ev_in, 0);
+    return err == hipSuccess ? MD_OK : fail("enter", err);
+  }
+  md_status leave() {
+    hipError_t err = hipEventRecord(ev_out, work);
+    if (err == hipSuccess) err = hipStreamWaitEvent(user, ev_out, 0);
+    return err == hipSuccess ? MD_OK : fail("leave", err);
+  }
+};
+
+struct md_system {
+  Engine *e;
+};
+struct md_batch {
+  Engine *e;
+};
+
+namespace {
+
+md_status engine_init(Engine *e, int max_slots, const md_allocator *a, void *stream) {
+  e->max_slots = max_slots;
+  e->rep.assign(max_slots, nullptr);
+  e->user = (hipStream_t)stream;
+  if (a) {
+    if (!a->alloc || !a->free) return MD_ERR_INVALID_ARG;
+    e->alloc = *a;
+    e->custom_alloc = true;
+  }
+  hipError_t err = hipStreamCreateWithFlags(&e->work, hipStreamNonBlocking);
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming);
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming);
+  if (err != hipSuccess) return e->fail("engine init", err);
+  e->d_slots = (SlotDev *)e->dmalloc(sizeof(SlotDev) * 2 * max_slots);
+  e->d_ctl = (CtlDev *)e->dmalloc(sizeof(CtlDev) * max_slots);
+  e->d_hdr = (int32_t *)e->dmalloc(256);
+  if (!e->d_slots || !e->d_ctl || !e->d_hdr) return MD_ERR_OOM;
+  err = hipHostMalloc((void **)&e->h_ctl, sizeof(CtlDev) * max_slots, hipHostMallocDefault);
+  if (err == hipSuccess)
+    err = hipHostMalloc((void **)&e->h_slots, sizeof(SlotDev) * 2 * max_slots,
+                        hipHostMallocDefault);
+  if (err != hipSuccess) return e->fail("pinned host buffers", err);
+  memset(e->h_ctl, 0, sizeof(CtlDev) * max_slots);
+  memset(e->h_slots, 0, sizeof(SlotDev) * 2 * max_slots);
+  err = hipMemsetAsync(e->d_ctl, 0, sizeof(CtlDev) * max_slots, e->work);
+  if (err == hipSuccess) err = hipMemsetAsync(e->d_slots, 0, sizeof(SlotDev) * 2 * max_slots, e->work);
+  if (err == hipSuccess) err = hipMemsetAsync(e->d_hdr, 0, 256, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  return err == hipSuccess ? MD_OK : e->fail("engine init", err);
+}
+
+void engine_free(Engine *e) {
+  if (!e) return;
+  if (e->work) (void)hipStreamSynchronize(e->work);
+  for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (int s = 0; s < PROFILE_SETS; ++s)
+    for (int k = 0; k < GRAPH_CHUNK; ++k)
+      for (int q = 0; q < 2; ++q)
+        if (e->prof_ev[s][k][q]) (void)hipEventDestroy(e->prof_ev[s][k][q]);
+  for (Replica *r : e->rep) {
+    if (!r) continue;
+    e->dfree(r->state);
+    e->dfree(r->hmat);
+    e->dfree(r->wmat);
+    delete r;
+  }
+  e->dfree(e->d_slots);
+  e->dfree(e->d_ctl);
+  e->dfree(e->d_hdr);
+  e->dfree(e->d_tile_rep);
+  e->dfree(e->d_ctile_rep);
+  if (e->h_ctl) (void)hipHostFree(e->h_ctl);
+  if (e->h_slots) (void)hipHostFree(e->h_slots);
+  if (e->h_tab) (void)hipHostFree(e->h_tab);
+  if (e->ev_in) (void)hipEventDestroy(e->ev_in);
+  if (e->ev_out) (void)hipEventDestroy(e->ev_out);
+  if (e->work) (void)hipStreamDestroy(e->work);
+  delete e;
+}
+
+// Fill both descriptor variants of a replica from its allocations.  Variant 1
+// swaps every buffer pair of variant 0.
+void describe(Replica *r) {
+  const Geometry &g = r->g;
+  const Layout l = layout(g);
+  const size_t np = g.npad, R = g.fp64 ? 8 : 4;
+  const size_t cells = (size_t)g.nctiles * CTILE;
+  char *b = (char *)r->state;
+  SlotDev d{};
+  double *pv = (double *)(b + l.pv);
+  for (int buf = 0; buf < 2; ++buf)
+    for (int a = 0; a < 3; ++a) {
+      d.P[buf][a] = pv + (buf * 3 + a) * np;
+      d.V[buf][a] = pv + (6 + buf * 3 + a) * np;
+    }
+  d.id = (int32_t *)(b + l.ids);
+  d.id_alt = d.id + np;
+  d.F = b + l.fu;
+  d.F_alt = b + l.fu + 3 * np * R;
+  d.UA = b + l.fu + 6 * np * R;
+  d.UA_alt = b + l.fu + 8 * np * R;
+  d.cell = (int32_t *)(b + l.cellm);
+  d.cell_alt = d.cell + np;
+  d.m = d.cell + 2 * np;
+  d.m_alt = d.cell + 3 * np;
+  d.perm = (int32_t *)(b + l.perm);
+  d.inv = d.perm + np;
+  for (int s = 0; s < 3; ++s) {
+    d.cnt[s] = (int32_t *)(b + l.cnt + s * round_up(cells * 4, 256));
+    d.H[s] = (int32_t *)((char *)r->hmat + s * round_up((size_t)g.ncell * g.hcap * 4, 256));
+    d.ovf[s] = (int32_t *)(b + l.ovf) + s * 2 * OVF_CAP;
+  }
+  d.ovf_n = (int32_t *)(b + l.ovf) + 3 * 2 * OVF_CAP;
+  d.cs = (int32_t *)(b + l.cs);
+  d.scan_st = (unsigned long long *)(b + l.scan);
+  d.part = (double *)(b + l.part);
+  d.vring = (unsigned long long *)(b + l.vring);
+  d.W = (int32_t *)r->wmat;
+  d.W_alt = r->wmat ? (int32_t *)((char *)r->wmat + w_bytes(g, g.mcap) / 2) : nullptr;
+  d.L = g.L;
+  d.halfL = 0.5 * g.L;
+  d.invW = (double)g.G / g.L;
+  d.rn2 = g.rn * g.rn;
+  d.rc2 = g.rc * g.rc;
+  d.dt = r->p.dt;
+  d.hdt = 0.5 * r->p.dt;
+  d.half_shell = 0.5 * g.shell;
+  d.ushift = (g.rc == std::pow(2.0, 1.0 / 6.0)) ? 1.0 : 0.0;
+  d.n = (int32_t)g.n;
+  d.G = g.G;
+  d.ncell = g.ncell;
+  d.hcap = g.hcap;
+  d.mcap = g.mcap;
+  d.npad = g.npad;
+  d.ntiles = g.ntiles;
+  d.nctiles = g.nctiles;
+  d.cpt = g.cpt;
+  d.fp64 = g.fp64 ? 1 : 0;
+  d.cell_only = g.cell_only ? 1 : 0;
+  SlotDev e = d;
+  for (int a = 0; a < 3; ++a) {
+    std::swap(e.P[0][a], e.P[1][a]);
+    std::swap(e.V[0][a], e.V[1][a]);
+  }
+  std::swap(e.id, e.id_alt);
+  std::swap(e.F, e.F_alt);
+  std::swap(e.UA, e.UA_alt);
+  std::swap(e.cell, e.cell_alt);
+  std::swap(e.m, e.m_alt);
+  std::swap(e.W, e.W_alt);
+  const int32_t to = r->dev[0].tile_off, co = r->dev[0].ctile_off;
+  r->dev[0] = d;
+  r->dev[1] = e;
+  for (int v = 0; v < 2; ++v) {
+    r->dev[v].tile_off = to;
+    r->dev[v].ctile_off = co;
+  }
+}
+
+// Rebuild the tile tables and upload the descriptors of every slot (sync).
+md_status upload_tables(Engine *e) {
+  hipError_t err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("upload tables", err);
+  int nt = 0, nct = 0;
+  for (int s = 0; s < e->max_slots; ++s) {
+    Replica *r = e->rep[s];
+    if (!r) continue;
+    for (int v = 0; v < 2; ++v) {
+      r->dev[v].tile_off = nt;
+      r->dev[v].ctile_off = nct;
+    }
+    nt += r->g.ntiles;
+    nct += r->g.nctiles;
+  }
+  if (nt > e->tile_cap || nct > e->ctile_cap) {
+    e->dfree(e->d_tile_rep);
+    e->dfree(e->d_ctile_rep);
+    e->tile_cap = std::max(nt, 2 * e->tile_cap);
+    e->ctile_cap = std::max(nct, 2 * e->ctile_cap);
+    e->d_tile_rep = (int32_t *)e->dmalloc((size_t)e->tile_cap * 4);
+    e->d_ctile_rep = (int32_t *)e->dmalloc((size_t)e->ctile_cap * 4);
+    if (!e->d_tile_rep || !e->d_ctile_rep) return MD_ERR_OOM;
+  }
+  const size_t need = 8 + (size_t)nt + (size_t)nct;
+  if (need > e->h_tab_cap) {
+    if (e->h_tab) (void)hipHostFree(e->h_tab);
+    e->h_tab_cap = std::max(need, 2 * e->h_tab_cap);
+    err = hipHostMalloc((void **)&e->h_tab, e->h_tab_cap * 4, hipHostMallocDefault);
+    if (err != hipSuccess) return e->fail("pinned tables", err);
+  }
+  int32_t *hdr = e->h_tab, *tr = e->h_tab + 8, *ctr = tr + nt;
+  memset(hdr, 0, 32);
+  hdr[HDR_NTILES] = nt;
+  hdr[HDR_NCTILES] = nct;
+  for (int s = 0; s < e->max_slots; ++s) {
+    Replica *r = e->rep[s];
+    if (!r) {
+      memset(&e->h_slots[2 * s], 0, 2 * sizeof(SlotDev));
+      continue;
+    }
+    for (int k = 0; k < r->g.ntiles; ++k) tr[r->dev[0].tile_off + k] = s;
+    for (int k = 0; k < r->g.nctiles; ++k) ctr[r->dev[0].ctile_off + k] = s;
+    e->h_slots[2 * s] = r->dev[0];
+    e->h_slots[2 * s + 1] = r->dev[1];
+  }
+  err = hipMemcpyAsync(e->d_hdr, hdr, 32, hipMemcpyHostToDevice, e->work);
+  if (err == hipSuccess && nt)
+    err = hipMemcpyAsync(e->d_tile_rep, tr, (size_t)nt * 4, hipMemcpyHostToDevice, e->work);
+  if (err == hipSuccess && nct)
+    err = hipMemcpyAsync(e->d_ctile_rep, ctr, (size_t)nct * 4, hipMemcpyHostToDevice, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(e->d_slots, e->h_slots, sizeof(SlotDev) * 2 * e->max_slots,
+                         hipMemcpyHostToDevice, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("upload tables", err);
+  if (!e->batch) {
+    e->grid = std::max(1, std::min(nt, MAX_GRID));
+    e->cgrid = std::max(1, std::min(nct, MAX_GRID));
+  }
+  return MD_OK;
+}
+
+md_status read_ctl(Engine *e) {
+  hipError_t err = hipStreamSynchronize(e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(e->h_ctl, e->d_ctl, sizeof(CtlDev) * e->max_slots,
+                         hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  return err == hipSuccess ? MD_OK : e->fail("read control blocks", err);
+}
+
+md_status write_ctl(Engine *e, int s) {
+  hipError_t err = hipMemcpyAsync(&e->d_ctl[s], &e->h_ctl[s], sizeof(CtlDev),
+                                  hipMemcpyHostToDevice, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  return err == hipSuccess ? MD_OK : e->fail("write control block", err);
+}
+
+md_status status_of(int err) {
+  if (err & ERR_NONFINITE) return MD_ERR_NONFINITE;
+  if (err & ERR_ESCAPED) return MD_ERR_ATOM_ESCAPED;
+  if (err & ERR_CELL) return MD_ERR_CELL_OVERFLOW;
+  if (err & ERR_SCAN) return MD_ERR_STATE;
+  return MD_OK;
+}
+
+md_status first_error(Engine *e, int only = -1) {
+  for (int s = 0; s < e->max_slots; ++s)
+    if (e->rep[s] && (only < 0 || s == only) && e->h_ctl[s].err) return status_of(e->h_ctl[s].err);
+  return MD_OK;
+}
+
+// Reorder the held state of the replicas into cell order (all, or `only`):
+// scan + ranks + gather into the alternate buffers, switch buffers, and bin
+// the held state again under its new indices.
+md_status reorder(Engine *e, int only) {
+  Tables T = e->tables();
+  launch_reorder(T, e->grid, e->cgrid, e->scan_epoch++, only, e->work);
+  launch_flip(T, only, e->work);
+  launch_clear_set(T, e->cgrid, only, e->work);
+  launch_insert(T, e->grid, 0, only, e->work);
+  return e->check("reorder launches");
+}
+
+// Wrap, bin, reorder and evaluate the held clean state of the replicas (all
+// or `only`): the creation-time evaluation (step 0's (b)-(e)), also used
+// after md_set_state.
+md_status evaluate_clean(Engine *e, int only, int mode, int force_build) {
+  Tables T = e->tables();
+  launch_clear_set(T, e->cgrid, only, e->work);
+  launch_insert(T, e->grid, 1, only, e->work);
+  md_status st = reorder(e, only);
+  if (st != MD_OK) return st;
+  launch_step(T, e->grid, 0, mode, force_build, only, e->work);
+  launch_props(T, only, e->work);
+  if ((st = e->check("evaluate launches")) != MD_OK) return st;
+  if ((st = read_ctl(e)) != MD_OK) return st;
+  return first_error(e, only);
+}
+
+md_status alloc_replica(Engine *e, const md_params *p, Replica **out) {
+  Geometry g;
+  md_status st = geometry(p, &g);
+  if (st != MD_OK) return st;
+  Replica *r = new (std::nothrow) Replica();
+  if (!r) return MD_ERR_OOM;
+  r->p = *p;
+  r->g = g;
+  r->bytes = total_bytes(g);
+  if (e->batch && e->used + r->bytes > e->budget) {
+    delete r;
+    return MD_ERR_OOM;
+  }
+  r->state = e->dmalloc(layout(g).total);
+  r->hmat = e->dmalloc(h_bytes(g, g.hcap));
+  r->wmat = g.mcap ? e->dmalloc(w_bytes(g, g.mcap)) : nullptr;
+  if (!r->state || !r->hmat || (g.mcap && !r->wmat)) {
+    e->dfree(r->state);
+    e->dfree(r->hmat);
+    e->dfree(r->wmat);
+    delete r;
+    return MD_ERR_OOM;
+  }
+  hipError_t err = hipMemsetAsync(r->state, 0, layout(g).total, e->work);
+  if (err == hipSuccess) err = hipMemsetAsync(r->hmat, 0, h_bytes(g, g.hcap), e->work);
+  if (err == hipSuccess && r->wmat) err = hipMemsetAsync(r->wmat, 0, w_bytes(g, g.mcap), e->work);
+  if (err != hipSuccess) {
+    e->dfree(r->state);
+    e->dfree(r->hmat);
+    e->dfree(r->wmat);
+    delete r;
+    return e->fail("clear replica", err);
+  }
+  describe(r);
+  *out = r;
+  return MD_OK;
+}
+
+void free_replica(Engine *e, Replica *r) {
+  (void)hipStreamSynchronize(e->work);
+  e->dfree(r->state);
+  e->dfree(r->hmat);
+  e->dfree(r->wmat);
+  delete r;
+}
+
+// Upload positions (n x 3) and velocities of a clean state `step` into the
+// buffers of descriptor variant `variant`; ids are reset to 0..n-1.
+md_status upload_state(Engine *e, Replica *r, int variant, int64_t step, const double *pos,
+                       const double *vel) {
+  const int64_t n = r->g.n;
+  double *h = nullptr;
+  hipError_t err =
+      hipHostMalloc((void **)&h, (size_t)n * 6 * 8 + (size_t)n * 4, hipHostMallocDefault);
+  if (err != hipSuccess) return e->fail("pinned staging", err);
+  int32_t *hid = (int32_t *)(h + 6 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a) {
+      h[a * n + i] = pos[3 * i + a];
+      h[(3 + a) * n + i] = vel[3 * i + a];
+    }
+    hid[i] = (int32_t)i;
+  }
+  const SlotDev &d = r->dev[variant];
+  const int pb = (int)(step & 1), vb = (int)((step + 1) & 1);
+  double *dst[6] = {d.P[pb][0], d.P[pb][1], d.P[pb][2], d.V[vb][0], d.V[vb][1], d.V[vb][2]};
+  for (int a = 0; a < 6 && err == hipSuccess; ++a)
+    err = hipMemcpyAsync(dst[a], h + a * n, (size_t)n * 8, hipMemcpyHostToDevice, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(d.id, hid, (size_t)n * 4, hipMemcpyHostToDevice, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  (void)hipHostFree(h);
+  return err == hipSuccess ? MD_OK : e->fail("upload state", err);
+}
+
+// Control block of a freshly (re)initialised clean state at `step`.
+void reset_ctl(CtlDev &c, int64_t step, int variant, int64_t n_rebuilds, int max_h) {
+  memset(&c, 0, sizeof(CtlDev));
+  c.done = c.target = c.base = step;
+  c.force_step = step;
+  c.err_step = INT64_MAX;
+  c.n_rebuilds = n_rebuilds;
+  c.clean = 1;
+  c.variant = variant;
+  c.max_h = max_h;
+}
+
+// Enlarge the cell-layer matrix of slot s after ERR_CELL and bin its held
+// state again (the state itself is intact: the overflowing binning was the
+// last thing the replica did).
+md_status repair_cells(Engine *e, int s) {
+  Replica *r = e->rep[s];
+  CtlDev &c = e->h_ctl[s];
+  const int hcap = std::max(2 * r->g.hcap, r->g.hcap + 16);
+  void *h = e->dmalloc(h_bytes(r->g, hcap));
+  if (!h) return MD_ERR_CELL_OVERFLOW;
+  hipError_t err = hipMemsetAsync(h, 0, h_bytes(r->g, hcap), e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("regrow", err);
+  e->dfree(r->hmat);
+  r->bytes += h_bytes(r->g, hcap) - h_bytes(r->g, r->g.hcap);
+  e->used += h_bytes(r->g, hcap) - h_bytes(r->g, r->g.hcap);
+  r->hmat = h;
+  r->g.hcap = hcap;
+  describe(r);
+  // all three sets start empty again (the counters live in the state block)
+  for (int q = 0; q < 3; ++q) {
+    err = hipMemsetAsync(r->dev[0].cnt[q], 0, (size_t)r->g.nctiles * CTILE * 4, e->work);
+    if (err != hipSuccess) return e->fail("regrow", err);
+  }
+  err = hipMemsetAsync(r->dev[0].ovf_n, 0, 3 * 4, e->work);
+  if (err != hipSuccess) return e->fail("regrow", err);
+  c.err &= ~ERR_CELL;
+  c.err_step = INT64_MAX;
+  md_status st = upload_tables(e);
+  if (st == MD_OK) st = write_ctl(e, s);
+  if (st != MD_OK) return st;
+  launch_insert(e->tables(), e->grid, 0, s, e->work);
+  return e->check("rebin");
+}
+
+hipGraphExec_t step_graph(Engine *e, int k) {
+  auto it = e->graphs.find(k);
+  if (it != e->graphs.end()) return it->second;
+  Tables T = e->tables();
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  hipError_t err = hipStreamBeginCapture(e->work, hipStreamCaptureModeThreadLocal);
+  if (err != hipSuccess) {
+    e->fail("begin capture", err);
+    return nullptr;
+  }
+  for (int s = 0; s < k; ++s) launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->work);
+  launch_replay_end(T, k, e->work);
+  err = hipStreamEndCapture(e->work, &g);
+  if (err == hipSuccess) err = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (err != hipSuccess) {
+    e->fail("graph capture", err);
+    return nullptr;
+  }
+  e->graphs[k] = x;
+  return x;
+}
+
+md_status prof_collect(Engine *e, int set) {
+  const int k = e->prof_pending[set];
+  if (!k) return MD_OK;
+  hipError_t err = hipEventSynchronize(e->prof_ev[set][k - 1][1]);
+  for (int s = 0; s < k && err == hipSuccess; ++s) {
+    float ms = 0.f;
+    err = hipEventElapsedTime(&ms, e->prof_ev[set][s][0], e->prof_ev[set][s][1]);
+    e->prof_ms += ms;
+  }
+  if (err != hipSuccess) return e->fail("profile events", err);
+  e->prof_launches += k;
+  e->prof_pending[set] = 0;
+  return MD_OK;
+}
+
+// K steps of every running replica, then the counter update.
+md_status replay(Engine *e, int k) {
+  if (e->profiling) {
+    const int set = e->prof_next;
+    e->prof_next = (set + 1) % PROFILE_SETS;
+    md_status st = prof_collect(e, set);
+    if (st != MD_OK) return st;
+    Tables T = e->tables();
+    for (int s = 0; s < k; ++s) {
+      hipError_t err = hipEventRecord(e->prof_ev[set][s][0], e->work);
+      launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->work);
+      if (err == hipSuccess) err = hipEventRecord(e->prof_ev[set][s][1], e->work);
+      if (err != hipSuccess) return e->fail("profile event record", err);
+    }
+    launch_replay_end(T, k, e->work);
+    e->prof_pending[set] = k;
+    return e->check("profiled step launches");
+  }
+  hipGraphExec_t x = step_graph(e, k);
+  if (!x) return MD_ERR_HIP;
+  hipError_t err = hipGraphLaunch(x, e->work);
+  return err == hipSuccess ? MD_OK : e->fail("graph launch", err);
+}
+
+// Advance a single system from absolute step `from` to `to`: replays end on
+// multiples of GRAPH_CHUNK, where the (still running) system is reordered.
+md_status run_steps(Engine *e, int64_t from, int64_t to) {
+  int64_t pos = from;
+  while (pos < to) {
+    const int64_t room = GRAPH_CHUNK - (pos % GRAPH_CHUNK);
+    const int64_t c = std::min<int64_t>(room, to - pos);
+    int k = GRAPH_CHUNK;
+    while (k > c) k >>= 1;
+    md_status st = replay(e, k);
+    if (st != MD_OK) return st;
+    pos += k;
+    if (pos % GRAPH_CHUNK == 0 && pos < to) {
+      if ((st = reorder(e, -1)) != MD_OK) return st;
+    }
+  }
+  return MD_OK;
+}
+
+// Synchronise and repair cell-layer overflows, resuming the remaining steps
+// of a single system.  Returns the first hard error.
+md_status settle(Engine *e) {
+  for (int round = 0; round < 8; ++round) {
+    md_status st = read_ctl(e);
+    if (st != MD_OK) return st;
+    bool repaired = false;
+    for (int s = 0; s < e->max_slots; ++s) {
+      if (!e->rep[s]) continue;
+      if (e->h_ctl[s].err != ERR_CELL) continue;
+      if ((st = repair_cells(e, s)) != MD_OK) return st;
+      repaired = true;
+      const CtlDev &c = e->h_ctl[s];
+      if (!e->batch && c.target > c.done) {
+        launch_set_target(e->tables(), s, c.target, e->work);
+        if ((st = run_steps(e, c.done, c.target)) != MD_OK) return st;
+      }
+    }
+    if (!repaired || e->batch) return MD_OK;
+  }
+  return MD_ERR_STATE;
+}
+
+// Copy the held state of a replica to the host in original order.
+md_status fetch(Engine *e, int s, double *pos, double *vel, double *force, double *u_atom,
+                double *w_atom, int32_t *cell_of_atom) {
+  Replica *r = e->rep[s];
+  const CtlDev &c = e->h_ctl[s];
+  const SlotDev &d = r->dev[c.variant & 1];
+  const int64_t n = r->g.n, np = r->g.npad;
+  const size_t R = r->g.fp64 ? 8 : 4;
+  const int64_t k = c.clean ? c.done : c.done + 1;
+  const int pb = (int)(k & 1), vb = (int)((c.clean ? k + 1 : k) & 1);
+  char *h = nullptr;
+  const size_t bytes = (size_t)n * (6 * 8 + 5 * R + 8);
+  hipError_t err = hipHostMalloc((void **)&h, bytes, hipHostMallocDefault);
+  if (err != hipSuccess) return e->fail("pinned staging", err);
+  double *hp = (double *)h;
+  char *hf = h + (size_t)n * 48;
+  int32_t *hid = (int32_t *)(hf + (size_t)n * 5 * R);
+  int32_t *hcell = hid + n;
+  const double *src[6] = {d.P[pb][0], d.P[pb][1], d.P[pb][2], d.V[vb][0], d.V[vb][1], d.V[vb][2]};
+  for (int a = 0; a < 6 && err == hipSuccess; ++a)
+    err = hipMemcpyAsync(hp + a * n, src[a], (size_t)n * 8, hipMemcpyDeviceToHost, e->work);
+  for (int a = 0; a < 3 && err == hipSuccess; ++a)
+    err = hipMemcpyAsync(hf + a * n * R, (char *)d.F + a * np * R, (size_t)n * R,
+                         hipMemcpyDeviceToHost, e->work);
+  for (int a = 0; a < 2 && err == hipSuccess; ++a)
+    err = hipMemcpyAsync(hf + (3 + a) * n * R, (char *)d.UA + a * np * R, (size_t)n * R,
+                         hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(hid, d.id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(hcell, d.cell, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) {
+    (void)hipHostFree(h);
+    return e->fail("fetch", err);
+  }
+  for (int64_t p = 0; p < n; ++p) {
+    const int64_t i = hid[p];
+    if (i < 0 || i >= n) continue;
+    for (int a = 0; a < 3; ++a) {
+      if (pos) pos[3 * i + a] = hp[a * n + p];
+      if (vel) vel[3 * i + a] = hp[(3 + a) * n + p];
+      if (force)
+        force[3 * i + a] = R == 8 ? ((double *)hf)[a * n + p] : (double)((float *)hf)[a * n + p];
+    }
+    if (u_atom) u_atom[i] = R == 8 ? ((double *)hf)[3 * n + p] : (double)((float *)hf)[3 * n + p];
+    if (w_atom) w_atom[i] = R == 8 ? ((double *)hf)[4 * n + p] : (double)((float *)hf)[4 * n + p];
+    if (cell_of_atom) cell_of_atom[i] = hcell[p];
+  }
+  (void)hipHostFree(h);
+  return MD_OK;
+}
+
+void fill_props(const Replica *r, const CtlDev &c, md_props_t *o) {
+  memset(o, 0, sizeof(*o));
+  const double n = (double)r->g.n;
+  o->ke = c.ke;
+  o->pe = c.pe;
+  o->virial = c.vir;
+  o->ke_per_atom = c.ke / n;
+  o->pe_per_atom = c.pe / n;
+  o->virial_per_atom = c.vir / n;
+  o->vmax = std::sqrt(c.vmax2);
+  o->n_pairs = r->g.cell_only ? 0 : c.sum_m / 2;
+  o->n_rebuilds = c.n_rebuilds;
+  o->step = c.done;
+  o->max_nebr = c.max_m;
+  o->max_cell = c.max_h;
+  o->cells_per_edge = r->g.G;
+  // displacement accumulated through the held step and the rule's verdict
+  // for the next one (the step kernel recomputes the same from the rings)
+  if (!r->g.cell_only && c.clean) {
+    const int64_t k = c.done + 1;
+    const double D2 = c.disp_ring[((k - 2) % 3 + 3) % 3];
+    double V1;
+    const uint64_t b = c.vmax_ring[((k - 1) % 3 + 3) % 3];
+    memcpy(&V1, &b, 8);
+    const bool rb1 = (k - 1 == c.force_step) || D2 > 0.5 * r->g.shell;
+    const double D1 = (rb1 ? 0.0 : D2) + std::sqrt(V1) * r->p.dt;
+    o->disp = D1;
+    o->rebuild_due = D1 > 0.5 * r->g.shell ? 1 : 0;
+  }
+}
+
+md_status sys_ok(md_system *s) {
+  if (!s || !s->e || !s->e->rep[0]) return MD_ERR_INVALID_ARG;
+  return s->e->sticky_hip ? MD_ERR_HIP : MD_OK;
+}
+
+// Synchronise a single system: repair, reduce the properties, read back.
+md_status sync_system(Engine *e) {
+  md_status st = settle(e);
+  if (st != MD_OK) return st;
+  launch_props(e->tables(), -1, e->work);
+  if ((st = e->check("props")) != MD_OK) return st;
+  if ((st = read_ctl(e)) != MD_OK) return st;
+  return first_error(e);
+}
+
+md_status require_clean(Engine *e) {
+  md_status st = sync_system(e);
+  if (st != MD_OK) return st;
+  return e->h_ctl[0].clean ? MD_OK : MD_ERR_STATE;
+}
+
+md_status set_force_step(Engine *e, int s) {
+  md_status st = read_ctl(e);
+  if (st != MD_OK) return st;
+  e->h_ctl[s].force_step = e->h_ctl[s].done;
+  return write_ctl(e, s);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *md_status_string(md_status s) {
+  switch (s) {
+    case MD_OK: return "ok";
+    case MD_ERR_INVALID_ARG: return "invalid argument";
+    case MD_ERR_BOX_TOO_SMALL: return "box too small: fewer than 3 cells per edge";
+    case MD_ERR_OOM: return "device memory allocation failed";
+    case MD_ERR_HIP: return "HIP runtime error";
+    case MD_ERR_NEBR_OVERFLOW: return "neighbour matrix capacity exceeded";
+    case MD_ERR_ATOM_ESCAPED: return "atom escaped the periodic region";
+    case MD_ERR_NONFINITE: return "non-finite coordinate";
+    case MD_ERR_STATE: return "operation not valid in the current state";
+    case MD_ERR_NO_SLOT: return "no free batch slot";
+    case MD_ERR_CELL_OVERFLOW: return "cell-layer capacity exceeded";
+  }
+  return "unknown status";
+}
+
+md_status md_cells_per_edge(const md_params *p, int32_t *G) {
+  if (!G) return MD_ERR_INVALID_ARG;
+  Geometry g;
+  md_status st = geometry(p, &g);
+  if (st == MD_OK) *G = g.G;
+  return st;
+}
+
+md_status md_query_bytes(const md_params *p, size_t *bytes) {
+  if (!bytes) return MD_ERR_INVALID_ARG;
+  Geometry g;
+  md_status st = geometry(p, &g);
+  if (st != MD_OK) return st;
+  *bytes = total_bytes(g);
+  return MD_OK;
+}
+
+md_status md_create(const md_params *p, const double *pos, const double *vel,
+                    const md_allocator *a, void *hip_stream, md_system **out) {
+  if (!p || !pos || !vel || !out) return MD_ERR_INVALID_ARG;
+  *out = nullptr;
+  Geometry g;
+  md_status st = geometry(p, &g);
+  if (st != MD_OK) return st;
+  Engine *e = new (std::nothrow) Engine();
+  if (!e) return MD_ERR_OOM;
+  Replica *r = nullptr;
+  st = engine_init(e, 1, a, hip_stream);
+  if (st == MD_OK) st = e->enter();
+  if (st == MD_OK) st = alloc_replica(e, p, &r);
+  if (st == MD_OK) {
+    e->rep[0] = r;
+    e->used += r->bytes;
+    st = upload_state(e, r, 0, 0, pos, vel);
+  }
+  if (st == MD_OK) {
+    reset_ctl(e->h_ctl[0], 0, 0, 0, 0);
+    st = write_ctl(e, 0);
+  }
+  if (st == MD_OK) st = upload_tables(e);
+  for (int attempt = 0; st == MD_OK && attempt < 4; ++attempt) {
+    st = evaluate_clean(e, -1, MODE_FORCES, 1);
+    if (st == MD_ERR_CELL_OVERFLOW) {
+      if ((st = repair_cells(e, 0)) != MD_OK) break;
+      st = MD_OK;
+      continue;
+    }
+    break;
+  }
+  if (st == MD_OK) st = e->leave();
+  if (st != MD_OK) {
+    engine_free(e);
+    return st;
+  }
+  md_system *s = new (std::nothrow) md_system{e};
+  if (!s) {
+    engine_free(e);
+    return MD_ERR_OOM;
+  }
+  *out = s;
+  return MD_OK;
+}
+
+md_status md_bin_cells(md_system *s) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = require_clean(e)) != MD_OK) return st;
+  // wrap + bin the held state, reorder, rebuild the list at these positions
+  Tables T = e->tables();
+  launch_clear_set(T, e->cgrid, -1, e->work);
+  launch_insert(T, e->grid, 1, -1, e->work);
+  if ((st = reorder(e, -1)) != MD_OK) return st;
+  if (!e->rep[0]->g.cell_only) launch_step(T, e->grid, 0, MODE_BUILD, 1, -1, e->work);
+  if ((st = e->check("bin launches")) != MD_OK) return st;
+  if ((st = sync_system(e)) != MD_OK) return st;
+  if ((st = set_force_step(e, 0)) != MD_OK) return st;
+  return e->leave();
+}
+
+md_status md_build_nebr(md_system *s) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  Engine *e = s->e;
+  if (e->rep[0]->g.cell_only) return MD_ERR_STATE;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = require_clean(e)) != MD_OK) return st;
+  launch_step(e->tables(), e->grid, 0, MODE_BUILD, 1, -1, e->work);
+  if ((st = sync_system(e)) != MD_OK) return st;
+  if ((st = set_force_step(e, 0)) != MD_OK) return st;
+  return e->leave();
+}
+
+md_status md_forces(md_system *s) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = require_clean(e)) != MD_OK) return st;
+  launch_step(e->tables(), e->grid, 0, MODE_FORCES, 0, -1, e->work);
+  if ((st = sync_system(e)) != MD_OK) return st;
+  return e->leave();
+}
+
+md_status md_step(md_system *s, int64_t n_steps) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (n_steps < 0) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  if (n_steps == 0) return MD_OK;
+  if ((st = e->enter()) != MD_OK) return st;
+  const int64_t from = e->host_target;
+  const int64_t to = from + n_steps;
+  Tables T = e->tables();
+  launch_set_target(T, 0, to, e->work);
+  launch_kick(T, e->grid, e->work);
+  if ((st = e->check("kick")) != MD_OK) return st;
+  // a run that passes a multiple of the period reorders there, in the
+  // drifted state; a call that starts on one does the same after its kick,
+  // so the storage order never depends on how the steps were split into calls
+  if (from > 0 && from % GRAPH_CHUNK == 0 && (st = reorder(e, -1)) != MD_OK) return st;
+  if ((st = run_steps(e, from, to)) != MD_OK) return st;
+  e->host_target = to;
+  return e->leave();
+}
+
+md_status md_props(md_system *s, md_props_t *out) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (!out) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  st = sync_system(e);
+  if (st == MD_OK || st == MD_ERR_NONFINITE || st == MD_ERR_ATOM_ESCAPED)
+    fill_props(e->rep[0], e->h_ctl[0], out);
+  md_status st2 = e->leave();
+  return st != MD_OK ? st : st2;
+}
+
+md_status md_get_state(md_system *s, double *pos, double *vel, double *force, int64_t *step) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = sync_system(e)) != MD_OK) return st;
+  if ((st = fetch(e, 0, pos, vel, force, nullptr, nullptr, nullptr)) != MD_OK) return st;
+  if (step) *step = e->h_ctl[0].done;
+  return e->leave();
+}
+
+md_status md_get_atom_energies(md_system *s, double *u_atom, double *w_atom) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = sync_system(e)) != MD_OK) return st;
+  if ((st = fetch(e, 0, nullptr, nullptr, nullptr, u_atom, w_atom, nullptr)) != MD_OK) return st;
+  return e->leave();
+}
+
+md_status md_set_state(md_system *s, const double *pos, const double *vel) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (!pos || !vel) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  st = sync_system(e);
+  if (st != MD_OK && st != MD_ERR_NONFINITE && st != MD_ERR_ATOM_ESCAPED) return st;
+  Replica *r = e->rep[0];
+  CtlDev &c = e->h_ctl[0];
+  const int64_t step = c.clean ? c.done : c.done + 1;
+  const int variant = c.variant & 1;
+  if ((st = upload_state(e, r, variant, step, pos, vel)) != MD_OK) return st;
+  reset_ctl(c, step, variant, c.n_rebuilds, c.max_h);
+  if ((st = write_ctl(e, 0)) != MD_OK) return st;
+  for (int q = 0; q < 3; ++q)
+    if (hipMemsetAsync(r->dev[0].cnt[q], 0, (size_t)r->g.nctiles * CTILE * 4, e->work) !=
+        hipSuccess)
+      return e->fail("clear sets");
+  if (hipMemsetAsync(r->dev[0].ovf_n, 0, 12, e->work) != hipSuccess) return e->fail("clear sets");
+  if (hipMemsetAsync(r->dev[0].vring, 0, 3 * VSPREAD * 16 * 8, e->work) != hipSuccess)
+    return e->fail("clear ring");
+  e->host_target = step;
+  if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
+  return e->leave();
+}
+
+md_status md_get_cells(md_system *s, int32_t *cell_of_atom) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (!cell_of_atom) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = sync_system(e)) != MD_OK) return st;
+  if ((st = fetch(e, 0, nullptr, nullptr, nullptr, nullptr, nullptr, cell_of_atom)) != MD_OK)
+    return st;
+  return e->leave();
+}
+
+md_status md_get_bins(md_system *s, int32_t *order, int32_t *cell_start) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = sync_system(e)) != MD_OK) return st;
+  Replica *r = e->rep[0];
+  const SlotDev &d = r->dev[e->h_ctl[0].variant & 1];
+  hipError_t err = hipSuccess;
+  if (order) err = hipMemcpyAsync(order, d.id, (size_t)r->g.n * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess && cell_start)
+    err = hipMemcpyAsync(cell_start, d.cs, (size_t)(r->g.ncell + 1) * 4, hipMemcpyDeviceToHost,
+                         e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("get bins", err);
+  return e->leave();
+}
+
+md_status md_get_pairs(md_system *s, int64_t cap, int32_t *pi, int32_t *pj, int64_t *n_out) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (!n_out || cap < 0 || (cap > 0 && (!pi || !pj))) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  Replica *r = e->rep[0];
+  if (r->g.cell_only) return MD_ERR_STATE;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = sync_system(e)) != MD_OK) return st;
+  const SlotDev &d = r->dev[e->h_ctl[0].variant & 1];
+  const int64_t n = r->g.n;
+  const size_t np = r->g.npad;
+  std::vector<int32_t> W((size_t)r->g.mcap * np), m(n), id(n);
+  hipError_t err = hipMemcpyAsync(W.data(), d.W, W.size() * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(m.data(), d.m, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(id.data(), d.id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("get pairs", err);
+  int64_t k = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    if (m[p] > r->g.mcap) return MD_ERR_NEBR_OVERFLOW;  // list incomplete for this atom
+    for (int q = 0; q < m[p]; ++q) {
+      const int j = W[(size_t)q * np + p] & J_MASK;
+      if (k < cap) {
+        pi[k] = id[p];
+        pj[k] = (j >= 0 && j < n) ? id[j] : -1;
+      }
+      ++k;
+    }
+  }
+  *n_out = k;
+  return e->leave();
+}
+
+md_status md_profile(md_system *s, int32_t enable) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  Engine *e = s->e;
+  hipError_t err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("profile", err);
+  if (enable) {
+    for (int set = 0; set < PROFILE_SETS; ++set)
+      for (int k = 0; k < GRAPH_CHUNK; ++k)
+        for (int q = 0; q < 2; ++q)
+          if (!e->prof_ev[set][k][q] &&
+              (err = hipEventCreate(&e->prof_ev[set][k][q])) != hipSuccess)
+            return e->fail("profile events", err);
+    e->prof_launches = 0;
+    e->prof_ms = 0.0;
+    e->prof_pending[0] = e->prof_pending[1] = 0;
+    e->profiling = true;
+  } else {
+    for (int set = 0; set < PROFILE_SETS; ++set)
+      if ((st = prof_collect(e, set)) != MD_OK) return st;
+    e->profiling = false;
+  }
+  return MD_OK;
+}
+
+md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (!launches || !total_ms) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  for (int set = 0; set < PROFILE_SETS; ++set)
+    if ((st = prof_collect(e, set)) != MD_OK) return st;
+  *launches = e->prof_launches;
+  *total_ms = e->prof_ms;
+  return MD_OK;
+}
+
+void md_destroy(md_system *s) {
+  if (!s) return;
+  engine_free(s->e);
+  delete s;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+md_status md_batch_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_run,
+                          const md_allocator *a, void *hip_stream, md_batch **out) {
+  if (!out || max_slots <= 0 || steps_per_run <= 0) return MD_ERR_INVALID_ARG;
+  // runs end on multiples of the reordering period in every replica's step count
+  if (steps_per_run > GRAPH_CHUNK || (GRAPH_CHUNK % steps_per_run) != 0) return MD_ERR_INVALID_ARG;
+  *out = nullptr;
+  Engine *e = new (std::nothrow) Engine();
+  if (!e) return MD_ERR_OOM;
+  e->batch = true;
+  e->budget = hbm_budget;
+  e->steps_per_run = steps_per_run;
+  e->grid = MAX_GRID;
+  e->cgrid = MAX_GRID;
+  md_status st = engine_init(e, max_slots, a, hip_stream);
+  if (st == MD_OK) st = upload_tables(e);
+  if (st != MD_OK) {
+    engine_free(e);
+    return st;
+  }
+  md_batch *b = new (std::nothrow) md_batch{e};
+  if (!b) {
+    engine_free(e);
+    return MD_ERR_OOM;
+  }
+  *out = b;
+  return MD_OK;
+}
+
+md_status md_batch_admit(md_batch *b, const md_params *p, const double *pos, const double *vel,
+                         int64_t n_steps, int32_t *slot) {
+  if (!b || !b->e || !p || !pos || !vel || !slot || n_steps < 0) return MD_ERR_INVALID_ARG;
+  Engine *e = b->e;
+  if (e->sticky_hip) return MD_ERR_HIP;
+  int s = -1;
+  for (int k = 0; k < e->max_slots; ++k)
+    if (!e->rep[k]) {
+      s = k;
+      break;
+    }
+  if (s < 0) return MD_ERR_NO_SLOT;
+  md_status st = e->enter();
+  if (st != MD_OK) return st;
+  Replica *r = nullptr;
+  if ((st = alloc_replica(e, p, &r)) != MD_OK) return st;
+  if ((st = upload_state(e, r, 0, 0, pos, vel)) != MD_OK) {
+    free_replica(e, r);
+    return st;
+  }
+  if ((st = read_ctl(e)) != MD_OK) {
+    free_replica(e, r);
+    return st;
+  }
+  e->rep[s] = r;
+  e->used += r->bytes;
+  reset_ctl(e->h_ctl[s], 0, 0, 0, 0);
+  if ((st = write_ctl(e, s)) == MD_OK) st = upload_tables(e);
+  for (int attempt = 0; st == MD_OK && attempt < 4; ++attempt) {
+    st = evaluate_clean(e, s, MODE_FORCES, 1);
+    if (st == MD_ERR_CELL_OVERFLOW) {
+      if ((st = repair_cells(e, s)) != MD_OK) break;
+      st = MD_OK;
+      continue;
+    }
+    break;
+  }
+  if (st == MD_OK) {
+    // the target is set only now, so the evaluation above saw a clean,
+    // finished replica; the next run kicks it
+    e->h_ctl[s].target = n_steps;
+    st = write_ctl(e, s);
+  }
+  if (st != MD_OK) {
+    e->used -= r->bytes;
+    e->rep[s] = nullptr;
+    free_replica(e, r);
+    e->h_ctl[s] = CtlDev{};
+    (void)write_ctl(e, s);
+    (void)upload_tables(e);
+    return st;
+  }
+  *slot = s;
+  return e->leave();
+}
+
+md_status md_batch_run(md_batch *b) {
+  if (!b || !b->e) return MD_ERR_INVALID_ARG;
+  Engine *e = b->e;
+  md_status st = e->enter();
+  if (st != MD_OK) return st;
+  launch_kick(e->tables(), e->grid, e->work);
+  if ((st = e->check("kick")) != MD_OK) return st;
+  if ((st = replay(e, e->steps_per_run)) != MD_OK) return st;
+  // every replica's step count is a multiple of the period after a full run
+  if (e->steps_per_run == GRAPH_CHUNK && (st = reorder(e, -1)) != MD_OK) return st;
+  return e->leave();
+}
+
+md_status md_batch_poll(md_batch *b, int32_t *done, int32_t cap, int32_t *n_done) {
+  if (!b || !b->e || !n_done || cap < 0 || (cap > 0 && !done)) return MD_ERR_INVALID_ARG;
+  Engine *e = b->e;
+  md_status st = e->enter();
+  if (st != MD_OK) return st;
+  if ((st = settle(e)) != MD_OK) return st;
+  int k = 0;
+  for (int s = 0; s < e->max_slots; ++s) {
+    if (!e->rep[s]) continue;
+    const CtlDev &c = e->h_ctl[s];
+    const bool finished = c.clean && c.done >= c.target;
+    if (finished || c.err != 0) {
+      if (k < cap) done[k] = s;
+      ++k;
+    }
+  }
+  *n_done = k;
+  return e->leave();
+}
+
+md_status md_batch_props(md_batch *b, int32_t slot, md_props_t *out) {
+  if (!b || !b->e || !out || slot < 0 || slot >= b->e->max_slots || !b->e->rep[slot])
+    return MD_ERR_INVALID_ARG;
+  Engine *e = b->e;
+  launch_props(e->tables(), slot, e->work);
+  md_status st = e->check("props");
+  if (st == MD_OK) st = read_ctl(e);
+  if (st != MD_OK) return st;
+  fill_props(e->rep[slot], e->h_ctl[slot], out);
+  return status_of(e->h_ctl[slot].err);
+}
+
+md_status md_batch_get_state(md_batch *b, int32_t slot, double *pos, double *vel, int64_t *step) {
+  if (!b || !b->e || slot < 0 || slot >= b->e->max_slots || !b->e->rep[slot])
+    return MD_ERR_INVALID_ARG;
+  Engine *e = b->e;
+  md_status st = read_ctl(e);
+  if (st != MD_OK) return st;
+  if ((st = fetch(e, slot, pos, vel, nullptr, nullptr, nullptr, nullptr)) != MD_OK) return st;
+  if (step) *step = e->h_ctl[slot].done;
+  return status_of(e->h_ctl[slot].err);
+}
+
+md_status md_batch_release(md_batch *b, int32_t slot) {
+  if (!b || !b->e || slot < 0 || slot >= b->e->max_slots || !b->e->rep[slot])
+    return MD_ERR_INVALID_ARG;
+  Engine *e = b->e;
+  Replica *r = e->rep[slot];
+  e->used -= r->bytes;
+  e->rep[slot] = nullptr;
+  free_replica(e, r);
+  e->h_ctl[slot] = CtlDev{};
+  md_status st = write_ctl(e, slot);
+  if (st != MD_OK) return st;
+  return upload_tables(e);
+}
+
+md_status md_batch_usage(md_batch *b, size_t *bytes, int32_t *n_systems) {
+  if (!b || !b->e || !bytes || !n_systems) return MD_ERR_INVALID_ARG;
+  int k = 0;
+  for (Replica *r : b->e->rep) k += r != nullptr;
+  *bytes = b->e->used;
+  *n_systems = k;
+  return MD_OK;
+}
+
+void md_batch_destroy(md_batch *b) {
+  if (!b) return;
+  engine_free(b->e);
+  delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,32 @@
+// md_kernels.h -- host-side launchers of the gfx950 kernels (md_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "md_device.h"
+
+namespace md {
+
+// Step (a) for clean replicas that have steps to go: kick, drift, binning.
+void launch_kick(const Tables &T, int grid, hipStream_t s);
+// One step (MODE_STEP, step index s of the replay) or an evaluation of the
+// held clean state (MODE_FORCES / MODE_BUILD).  only >= 0: that replica only.
+void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int force_build,
+                 int only, hipStream_t s);
+// Advance the step counters after a replay of K steps.
+void launch_replay_end(const Tables &T, int K, hipStream_t s);
+// target = target; base = done (one replica).
+void launch_set_target(const Tables &T, int slot, long long target, hipStream_t s);
+// Reduce the property partials into the control blocks.
+void launch_props(const Tables &T, int only, hipStream_t s);
+// Bin the held state into its cell-layer set (optionally wrapping in place).
+void launch_insert(const Tables &T, int grid, int wrap_store, int only, hipStream_t s);
+// Reordering into cell order: scan, ranks, gather into the alternate buffers.
+void launch_reorder(const Tables &T, int grid, int cgrid, unsigned epoch, int only,
+                    hipStream_t s);
+// Make the alternate buffers current.
+void launch_flip(const Tables &T, int only, hipStream_t s);
+// Clear the held state's cell-layer set.
+void launch_clear_set(const Tables &T, int cgrid, int only, hipStream_t s);
+
+}  // namespace md

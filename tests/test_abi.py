@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every entry point include/md.h
+declares; host-only calls (geometry, sizing, status text) work without a GPU.
+No device work is started here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_0911_5631_amd import _lib
+from paper_0911_5631_amd.md import make_params, md_cells_per_edge, md_query_bytes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "md.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = _header_functions()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_status_strings():
+    L = _lib.lib()
+    for code in _lib.STATUS:
+        assert L.md_status_string(code)
+    assert L.md_status_string(-2).decode().startswith("box too small")
+
+
+def test_cells_per_edge_and_validation():
+    RC = 2.0 ** (1.0 / 6.0)
+    p = make_params(256000, 68.39903786706787, shell=0.4)
+    assert md_cells_per_edge(p) == 44
+    p = make_params(2048, 13.679807573413574, shell=0.0, precision="fp64")
+    assert md_cells_per_edge(p) == 12
+    p = make_params(110592, 48 / 0.8 ** (1 / 3), shell=0.4, even_cells=True)
+    assert md_cells_per_edge(p) ** 3 == 32768           # Table 5, delta = 0.4
+    with pytest.raises(_lib.MDError) as e:
+        md_cells_per_edge(make_params(100, 3.0, shell=0.4))
+    assert e.value.code == -2                           # G < 3
+    for bad in (make_params(0, 10.0), make_params(10, -1.0), make_params(10, 10.0, dt=0.0),
+                make_params(1 << 26, 1000.0)):
+        with pytest.raises(_lib.MDError) as e:
+            md_query_bytes(bad)
+        assert e.value.code == -1
+    assert RC > 1.12
+
+
+def test_query_bytes_scales_with_atoms():
+    a = md_query_bytes(make_params(256000, 68.39903786706787))
+    b = md_query_bytes(make_params(4000000, 170.99759466766967))
+    assert 200 * 256000 < a < 1000 * 256000
+    assert 14 < b / a < 17
+
+
+def test_product_path_has_no_fallback(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.lib()
