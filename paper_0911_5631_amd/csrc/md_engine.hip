@@ -155,6 +155,7 @@ struct Engine {
   int steps_per_run = GRAPH_CHUNK;
   unsigned scan_epoch = 1;
   int64_t host_target = 0;      // single system: target of the last md_step
+  int prec = 0;                 // PREC_* bits of the admitted replicas (step-kernel variants)
   // profiling of the step kernel (eager launches bracketed by events: events
   // recorded by graph nodes cannot be timed with hipEventElapsedTime)
   bool profiling = false;
@@ -478,7 +479,7 @@ md_status evaluate_clean(Engine *e, int only, int mode, int force_build) {
   launch_insert(T, e->grid, 1, only, e->work);
   md_status st = reorder(e, only);
   if (st != MD_OK) return st;
-  launch_step(T, e->grid, 0, mode, force_build, only, e->work);
+  launch_step(T, e->grid, 0, mode, force_build, only, e->prec, e->work);
   launch_props(T, only, e->work);
   if ((st = e->check("evaluate launches")) != MD_OK) return st;
   if ((st = read_ctl(e)) != MD_OK) return st;
@@ -519,6 +520,7 @@ md_status alloc_replica(Engine *e, const md_params *p, Replica **out) {
     return e->fail("clear replica", err);
   }
   describe(r);
+  e->prec |= g.fp64 ? PREC_FP64 : PREC_FP32;
   *out = r;
   return MD_OK;
 }
@@ -607,7 +609,8 @@ md_status repair_cells(Engine *e, int s) {
 }
 
 hipGraphExec_t step_graph(Engine *e, int k) {
-  auto it = e->graphs.find(k);
+  const int key = k * 4 + e->prec;
+  auto it = e->graphs.find(key);
   if (it != e->graphs.end()) return it->second;
   Tables T = e->tables();
   hipGraph_t g = nullptr;
@@ -617,7 +620,7 @@ hipGraphExec_t step_graph(Engine *e, int k) {
     e->fail("begin capture", err);
     return nullptr;
   }
-  for (int s = 0; s < k; ++s) launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->work);
+  for (int s = 0; s < k; ++s) launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work);
   launch_replay_end(T, k, e->work);
   err = hipStreamEndCapture(e->work, &g);
   if (err == hipSuccess) err = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
@@ -626,7 +629,7 @@ hipGraphExec_t step_graph(Engine *e, int k) {
     e->fail("graph capture", err);
     return nullptr;
   }
-  e->graphs[k] = x;
+  e->graphs[key] = x;
   return x;
 }
 
@@ -655,7 +658,7 @@ md_status replay(Engine *e, int k) {
     Tables T = e->tables();
     for (int s = 0; s < k; ++s) {
       hipError_t err = hipEventRecord(e->prof_ev[set][s][0], e->work);
-      launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->work);
+      launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work);
       if (err == hipSuccess) err = hipEventRecord(e->prof_ev[set][s][1], e->work);
       if (err != hipSuccess) return e->fail("profile event record", err);
     }
@@ -921,7 +924,7 @@ md_status md_bin_cells(md_system *s) {
   launch_clear_set(T, e->cgrid, -1, e->work);
   launch_insert(T, e->grid, 1, -1, e->work);
   if ((st = reorder(e, -1)) != MD_OK) return st;
-  if (!e->rep[0]->g.cell_only) launch_step(T, e->grid, 0, MODE_BUILD, 1, -1, e->work);
+  if (!e->rep[0]->g.cell_only) launch_step(T, e->grid, 0, MODE_BUILD, 1, -1, e->prec, e->work);
   if ((st = e->check("bin launches")) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
   if ((st = set_force_step(e, 0)) != MD_OK) return st;
@@ -935,7 +938,7 @@ md_status md_build_nebr(md_system *s) {
   if (e->rep[0]->g.cell_only) return MD_ERR_STATE;
   if ((st = e->enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
-  launch_step(e->tables(), e->grid, 0, MODE_BUILD, 1, -1, e->work);
+  launch_step(e->tables(), e->grid, 0, MODE_BUILD, 1, -1, e->prec, e->work);
   if ((st = sync_system(e)) != MD_OK) return st;
   if ((st = set_force_step(e, 0)) != MD_OK) return st;
   return e->leave();
@@ -947,7 +950,7 @@ md_status md_forces(md_system *s) {
   Engine *e = s->e;
   if ((st = e->enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
-  launch_step(e->tables(), e->grid, 0, MODE_FORCES, 0, -1, e->work);
+  launch_step(e->tables(), e->grid, 0, MODE_FORCES, 0, -1, e->prec, e->work);
   if ((st = sync_system(e)) != MD_OK) return st;
   return e->leave();
 }

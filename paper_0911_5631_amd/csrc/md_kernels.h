@@ -9,10 +9,13 @@ namespace md {
 
 // Step (a) for clean replicas that have steps to go: kick, drift, binning.
 void launch_kick(const Tables &T, int grid, hipStream_t s);
+// Precisions present in an engine (bit mask): one step-kernel variant each.
+enum { PREC_FP32 = 1, PREC_FP64 = 2 };
+
 // One step (MODE_STEP, step index s of the replay) or an evaluation of the
 // held clean state (MODE_FORCES / MODE_BUILD).  only >= 0: that replica only.
 void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int force_build,
-                 int only, hipStream_t s);
+                 int only, int precisions, hipStream_t s);
 // Advance the step counters after a replay of K steps.
 void launch_replay_end(const Tables &T, int K, hipStream_t s);
 // target = target; base = done (one replica).

@@ -294,9 +294,59 @@ __device__ __forceinline__ double img_shift(uint32_t code, double L) {
   return code == 0 ? 0.0 : (code == 1 ? L : -L);
 }
 
+// Compare-exchange network ordering eight values (Batcher odd-even merge).
+#define MD_CX(p, q)                        \
+  {                                        \
+    const int lo_ = min(p, q), hi_ = max(p, q); \
+    p = lo_;                               \
+    q = hi_;                               \
+  }
+__device__ __forceinline__ void sort8(int (&v)[8]) {
+  MD_CX(v[0], v[1]) MD_CX(v[2], v[3]) MD_CX(v[4], v[5]) MD_CX(v[6], v[7])
+  MD_CX(v[0], v[2]) MD_CX(v[1], v[3]) MD_CX(v[4], v[6]) MD_CX(v[5], v[7])
+  MD_CX(v[1], v[2]) MD_CX(v[5], v[6])
+  MD_CX(v[0], v[4]) MD_CX(v[1], v[5]) MD_CX(v[2], v[6]) MD_CX(v[3], v[7])
+  MD_CX(v[2], v[4]) MD_CX(v[3], v[5])
+  MD_CX(v[1], v[2]) MD_CX(v[3], v[4]) MD_CX(v[5], v[6])
+}
+#undef MD_CX
+
+// Neighbour cell number q (0..26; offsets z-major, x fastest) of the cell
+// (cx, cy, cz), with the periodic image code of its atoms and their shifts.
+struct NCell {
+  int c;
+  uint32_t code;
+  double bx, by, bz;
+};
+__device__ __forceinline__ NCell ncell(int q, int cx, int cy, int cz, int G, double L) {
+  int n[3] = {cx + q % 3 - 1, cy + (q / 3) % 3 - 1, cz + q / 9 - 1};
+  uint32_t im[3];
+  for (int a = 0; a < 3; ++a) {
+    im[a] = 0;
+    if (n[a] >= G) {
+      n[a] -= G;
+      im[a] = 2;
+    } else if (n[a] < 0) {
+      n[a] += G;
+      im[a] = 1;
+    }
+  }
+  NCell r;
+  r.c = (n[2] * G + n[1]) * G + n[0];
+  r.code = (im[0] | (im[1] << 2) | (im[2] << 4)) << J_BITS;
+  r.bx = img_shift(im[0], L);
+  r.by = img_shift(im[1], L);
+  r.bz = img_shift(im[2], L);
+  return r;
+}
+
 // 27-cell traversal (offsets z-major, x fastest; ascending index within a
 // cell) around the wrapped position of atom i.  Accepts r^2 < r_n^2 into W
 // when building, and accumulates the forces of pairs with r^2 < r_c^2.
+// The occupancy and the first four row entries of the next cell are loaded
+// while the current cell is evaluated; a cell's atoms are ordered with a
+// sorting network and their coordinates loaded four at a time.  Cells with
+// more than eight atoms take the general path.
 template <typename R>
 __device__ __forceinline__ int traverse_cells(const SlotDev &S, int set, int i, int ci,
                                               const double *__restrict__ X,
@@ -306,61 +356,75 @@ __device__ __forceinline__ int traverse_cells(const SlotDev &S, int set, int i, 
   const int G = S.G;
   const double L = S.L, halfL = S.halfL, rn2 = S.rn2, rc2 = S.rc2;
   const R ushift = (R)S.ushift;
-  const int mcap = S.mcap;
+  const int mcap = S.mcap, hcap = S.hcap;
   int32_t *__restrict__ Wc = S.W + i;
   const size_t np = (size_t)S.npad;
+  const int32_t *__restrict__ CNT = S.cnt[set];
+  const int32_t *__restrict__ HS = S.H[set];
   const int cx = ci % G, cy = (ci / G) % G, cz = ci / (G * G);
+  const bool fast = hcap >= 8;
   int m = 0;
-  for (int oz = -1; oz <= 1; ++oz) {
-    int nz = cz + oz;
-    uint32_t iz = 0;
-    if (nz >= G) {
-      nz -= G;
-      iz = 2;
-    } else if (nz < 0) {
-      nz += G;
-      iz = 1;
-    }
-    const double bz = img_shift(iz, L);
-    for (int oy = -1; oy <= 1; ++oy) {
-      int ny = cy + oy;
-      uint32_t iy = 0;
-      if (ny >= G) {
-        ny -= G;
-        iy = 2;
-      } else if (ny < 0) {
-        ny += G;
-        iy = 1;
+  auto accept = [&](int j, const NCell &nc, double xj, double yj, double zj) {
+    const double dx = (xi - wrap1(xj, L, halfL)) + nc.bx;
+    const double dy = (yi - wrap1(yj, L, halfL)) + nc.by;
+    const double dz = (zi - wrap1(zj, L, halfL)) + nc.bz;
+    const double s = (dx * dx + dy * dy) + dz * dz;
+    if (s < rn2) {
+      if (build) {
+        if (m < mcap) Wc[(size_t)m * np] = (int32_t)((uint32_t)j | nc.code);
+        ++m;
       }
-      const double by = img_shift(iy, L);
-      for (int ox = -1; ox <= 1; ++ox) {
-        int nx = cx + ox;
-        uint32_t ix = 0;
-        if (nx >= G) {
-          nx -= G;
-          ix = 2;
-        } else if (nx < 0) {
-          nx += G;
-          ix = 1;
-        }
-        const double bx = img_shift(ix, L);
-        const uint32_t code = (ix | (iy << 2) | (iz << 4)) << J_BITS;
-        visit_cell(S, set, (nz * G + ny) * G + nx, [&](int j) {
-          if (j == i) return;
-          const double dx = (xi - wrap1(X[j], L, halfL)) + bx;
-          const double dy = (yi - wrap1(Y[j], L, halfL)) + by;
-          const double dz = (zi - wrap1(Z[j], L, halfL)) + bz;
-          const double s = (dx * dx + dy * dy) + dz * dz;
-          if (s < rn2) {
-            if (build) {
-              if (m < mcap) Wc[(size_t)m * np] = (int32_t)((uint32_t)j | code);
-              ++m;
-            }
-            if (force && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
-          }
-        });
-      }
+      if (force && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
     }
+  };
+  // evaluate four ordered candidates (INT_MAX marks an empty place)
+  auto four = [&](const NCell &nc, int v0, int v1, int v2, int v3) {
+    const int vv[4] = {v0, v1, v2, v3};
+    double xj[4], yj[4], zj[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = vv[e] != INT_MAX ? vv[e] : i;
+      xj[e] = X[j];
+      yj[e] = Y[j];
+      zj[e] = Z[j];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (vv[e] != INT_MAX && vv[e] != i) accept(vv[e], nc, xj[e], yj[e], zj[e]);
+  };
+  NCell cur = ncell(0, cx, cy, cz, G, L);
+  int ccnt = CNT[cur.c];
+  int crow[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) crow[e] = fast ? HS[(size_t)cur.c * hcap + e] : 0;
+  for (int q = 0; q < 27; ++q) {
+    NCell nxt = cur;
+    int ncnt = 0;
+    int nrow[4] = {0, 0, 0, 0};
+    if (q < 26) {
+      nxt = ncell(q + 1, cx, cy, cz, G, L);
+      ncnt = CNT[nxt.c];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) nrow[e] = fast ? HS[(size_t)nxt.c * hcap + e] : 0;
+    }
+    if (fast && ccnt <= 8) {
+      int v[8];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = e < ccnt ? crow[e] : INT_MAX;
+#pragma unroll
+      for (int e = 4; e < 8; ++e) v[e] = e < ccnt ? HS[(size_t)cur.c * hcap + e] : INT_MAX;
+      sort8(v);
+      four(cur, v[0], v[1], v[2], v[3]);
+      if (ccnt > 4) four(cur, v[4], v[5], v[6], v[7]);
+    } else {
+      visit_cell(S, set, cur.c, [&](int j) {
+        if (j != i) accept(j, cur, X[j], Y[j], Z[j]);
+      });
+    }
+    cur = nxt;
+    ccnt = ncnt;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) crow[e] = nrow[e];
   }
   return m;
 }
@@ -551,13 +615,15 @@ __device__ void step_tile(const SlotDev &S, CtlDev &C, int lt, int64_t k, int mo
   __syncthreads();
 }
 
-__global__ __launch_bounds__(TILE) void k_step(Tables T, int s, int mode, int force_build,
+template <typename R>
+__global__ __launch_bounds__(TILE, 4) void k_step(Tables T, int s, int mode, int force_build,
                                                int only) {
   const int nt = T.hdr[HDR_NTILES];
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
     const int r = T.tile_rep[t];
     if (only >= 0 && r != only) continue;
     const SlotDev &S = slot_of(T, r);
+    if (S.fp64 != (sizeof(R) == 8)) continue;  // the other precision's kernel
     CtlDev &C = T.ctl[r];
     int64_t k;
     bool last = false, cells, build;
@@ -583,10 +649,7 @@ __global__ __launch_bounds__(TILE) void k_step(Tables T, int s, int mode, int fo
     // binning r(k+1), err_step = k + 1) must not stop the other workgroups
     if (C.err != 0 && C.err_step <= k) continue;
     const int lt = t - S.tile_off;
-    if (S.fp64)
-      step_tile<double>(S, C, lt, k, mode, cells, build, last);
-    else
-      step_tile<float>(S, C, lt, k, mode, cells, build, last);
+    step_tile<R>(S, C, lt, k, mode, cells, build, last);
     if (mode == MODE_STEP && lt == 0 && threadIdx.x == 0) {
       // the one writer of these ring slots in this launch
       if (!S.cell_only) {
@@ -910,9 +973,13 @@ void launch_kick(const Tables &T, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_kick_end, dim3((T.nslots + TILE - 1) / TILE), dim3(TILE), 0, s, T);
 }
 void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int force_build,
-                 int only, hipStream_t s) {
-  hipLaunchKernelGGL(k_step, dim3(grid), dim3(TILE), 0, s, T, step_in_replay, mode, force_build,
-                     only);
+                 int only, int precisions, hipStream_t s) {
+  if (precisions & PREC_FP32)
+    hipLaunchKernelGGL(k_step<float>, dim3(grid), dim3(TILE), 0, s, T, step_in_replay, mode,
+                       force_build, only);
+  if (precisions & PREC_FP64)
+    hipLaunchKernelGGL(k_step<double>, dim3(grid), dim3(TILE), 0, s, T, step_in_replay, mode,
+                       force_build, only);
 }
 void launch_replay_end(const Tables &T, int K, hipStream_t s) {
   hipLaunchKernelGGL(k_replay_end, dim3((T.nslots + TILE - 1) / TILE), dim3(TILE), 0, s, T, K);
