@@ -9,9 +9,11 @@ A "step" is one leapfrog time step of the whole system: (a) kick+drift,
 start with random velocity directions) and resident in HBM before timing.
 
 Prints ONE JSON line.  Besides the throughput it reports
-  roofline      the force kernel (the per-step kernel) against HBM bandwidth,
-                with its average duration measured by HIP events recorded
-                around every launch inside the timed graphs;
+  roofline      the step kernel k_step (forces, list build at rebuilds,
+                integration, binning: the dominant kernel) against HBM
+                bandwidth: algorithmic bytes per launch over its average
+                duration, measured with HIP events around every launch on the
+                library's stream in a second region of the same length;
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample of
                 the same workload (one core).
 """
@@ -30,15 +32,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "atom-steps/s soft-sphere ρ=0.8 (single vs batched); p50/p99 request latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_sp256000_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sp256000_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_0911_5631_amd", "csrc", "md_kernels.hip")
 
 
-def force_bytes_per_atom(mean_m: float) -> float:
-    """Algorithmic HBM bytes per atom of one force-kernel launch (a list step):
-    read r_i (24) + v_i (24) + m_i (4) + W column (4 m) ; write v_i (24) +
-    r_i(t+1) (24).  Neighbour coordinates are counted as cache hits."""
-    return 100.0 + 4.0 * mean_m
+def step_bytes_per_atom(mean_m: float, rebuild_frac: float) -> float:
+    """Algorithmic HBM bytes per atom of one k_step launch.  A list step reads
+    r_i and v_i (48), the list length (4) and the list (4 m) and writes
+    r_i(t+dt) and v_i (48); a rebuild writes the list instead of reading it,
+    plus the length and reads the atom's cell (8 more).  Neighbour
+    coordinates count as cache hits (each is read once per step by the tile
+    windows)."""
+    return 100.0 + 4.0 * mean_m + 8.0 * rebuild_frac
+
+
+def model_bytes_per_atom_step(mean_m: float, rebuild_frac: float) -> float:
+    """Whole-step model (fused step + amortised sort and build): the fused
+    step above, plus per rebuild the binning (read r 24, cell 8, counts ~3),
+    the sorted scatter (52 read + 52 written) and the build (24 + 4 m + 4)."""
+    per_rebuild = 24 + 8 + 3 + 104 + 24 + 4.0 * mean_m + 4
+    return 100.0 + 4.0 * mean_m + rebuild_frac * per_rebuild
 
 
 def kernel_sha() -> str:
@@ -87,6 +100,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample (0: skip)")
     ap.add_argument("--workload", default="sp_256k", choices=["sp_256k", "sp_4m", "sp_small"])
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (a counter calibration "
+                         "point for profilers), untimed")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs each system on a single MI355X "
@@ -98,12 +114,20 @@ def main() -> int:
     from paper_0911_5631_amd.md import System
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy > 0:
+        nel = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = {"sp_256k": I.sp_256k, "sp_4m": I.sp_4m, "sp_small": I.sp_small_cells}[args.workload]()
     n = wl.n
     s = System(wl.pos, wl.vel, wl.box, shell=wl.shell, dt=wl.dt, precision=wl.precision)
     print(f"# created {wl.name}: N={n} L={wl.box:.4f}", file=sys.stderr, flush=True)
     s.step(args.warmup)
-    s.props()
+    p0 = s.props()
     torch.cuda.synchronize()
 
     # timed region: K steps replayed from the captured step graphs
@@ -130,10 +154,12 @@ def main() -> int:
           f"{kern_ms / max(launches, 1) * 1e3:.2f} us avg", file=sys.stderr, flush=True)
 
     mean_m = 2.0 * pr["n_pairs"] / n
+    rebuild_frac = (pr["n_rebuilds"] - p0["n_rebuilds"]) / args.steps
     avg_s = kern_ms * 1e-3 / max(launches, 1)
-    bytes_launch = force_bytes_per_atom(mean_m) * n
+    bytes_launch = step_bytes_per_atom(mean_m, rebuild_frac) * n
     achieved = bytes_launch / avg_s / 1e9
     traffic = traffic_per_launch()
+    model_b = model_bytes_per_atom_step(mean_m, rebuild_frac)
     out = {
         "metric": METRIC,
         "value": value,
@@ -150,12 +176,15 @@ def main() -> int:
         "config": {"workload": wl.name, "n_atoms": n, "density": wl.rho,
                    "temperature": wl.temperature, "shell": wl.shell, "dt": wl.dt,
                    "box": wl.box, "parallelism": "single-gpu"},
-        "roofline": {"bound": "hbm", "kernel": "k_force", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_step", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": bytes_launch,
                      "avg_launch_us": avg_s * 1e6, "launches": launches,
                      "profiled_region_atom_steps_per_s": n * args.steps / (t3 - t2),
-                     "mean_neighbours": mean_m},
+                     "mean_neighbours": mean_m, "rebuild_fraction": rebuild_frac},
+        "step_model": {"bytes_per_atom_step": model_b,
+                       "roofline_atom_steps_per_s": HBM_PEAK_GBS * 1e9 / model_b,
+                       "frac": value * model_b / (HBM_PEAK_GBS * 1e9)},
         "props": {"ke_per_atom": pr["ke_per_atom"], "pe_per_atom": pr["pe_per_atom"],
                   "n_rebuilds": pr["n_rebuilds"], "step": pr["step"]},
     }

@@ -10,10 +10,11 @@
  *
  * The path per time step (Sec. 2.1, loop steps (a)-(e)):
  *   (a) half-step velocity update and full-step position update (leapfrog);
- *   (b) when a rebuild is due: periodic wrap, cell binning (cell assignment,
- *       layer assignment, cell-order reordering: Secs. 2.4-2.5) and the
- *       neighbour-matrix build over 27 cells without Newton's third law
- *       (Secs. 2.3-2.4);
+ *   (b) when a rebuild is due: periodic wrap, cell binning (cell assignment
+ *       and layer assignment, Secs. 2.2 and 2.4), reordering of the atoms
+ *       into cell order (Sec. 2.5; done at every rebuild, as a stable
+ *       counting sort) and the neighbour-matrix build over 27 cells without
+ *       Newton's third law (Secs. 2.3-2.4);
  *   (c) forces and potential energy from the neighbour matrix (Sec. 2.4);
  *   (d) second half-step velocity update;
  *   (e) kinetic energy, maximum speed and the rebuild decision: the list is
@@ -30,17 +31,19 @@
  *   - Ownership: the library copies host inputs and owns all device memory,
  *     which it obtains through the caller's md_allocator (NULL: hipMalloc /
  *     hipFree).  Host buffers passed in are never retained.
- *   - Streams: every device operation of a system is enqueued on the HIP
- *     stream given at creation (NULL: the null stream).  Calls marked
- *     "async" return before the device work completes; calls marked
- *     "sync" synchronise that stream first.
- *   - Errors found on the device (neighbour-matrix or cell-layer overflow,
- *     an escaped atom, a non-finite coordinate) are latched in the system,
- *     stop all further device work on it, and are returned by the next
- *     synchronising call.  Neighbour-matrix and cell-layer overflows are
- *     repaired inside md_step / md_forces / md_build_nebr by enlarging the
- *     capacity and redoing the interrupted work; they surface as errors only
- *     if the larger allocation fails.  MD_ERR_HIP is sticky: after it only
+ *   - Streams: device work is ordered after everything already enqueued on
+ *     the HIP stream given at creation (NULL: the null stream), and later
+ *     work on that stream waits for it.  Calls marked "async" return before
+ *     the device work completes; calls marked "sync" wait for it.
+ *   - Errors found on the device (an escaped atom, a non-finite coordinate)
+ *     are latched in the system, stop its device work at the step where
+ *     they arose, and are returned by the next synchronising call.  A cell
+ *     whose occupancy exceeds the layer capacity spills into an overflow
+ *     list; when that fills too, the library enlarges the capacity and
+ *     resumes the interrupted steps (error only if the allocation fails).
+ *     An atom whose neighbour list exceeds nebr_cap is evaluated from the
+ *     cells instead (same pairs, exact), and md_get_pairs reports
+ *     MD_ERR_NEBR_OVERFLOW.  MD_ERR_HIP is sticky: after it only
  *     md_destroy / md_batch_destroy is valid.
  *   - Threading: one host thread at a time per md_system / md_batch.
  */
@@ -63,7 +66,7 @@ typedef enum {
     MD_ERR_BOX_TOO_SMALL = -2, /* fewer than 3 cells per edge (G = floor(L / r_n) < 3) */
     MD_ERR_OOM = -3,           /* the allocator returned NULL */
     MD_ERR_HIP = -4,           /* a HIP runtime call failed (sticky) */
-    MD_ERR_NEBR_OVERFLOW = -5, /* neighbour matrix could not be enlarged */
+    MD_ERR_NEBR_OVERFLOW = -5, /* md_get_pairs: a list exceeded nebr_cap */
     MD_ERR_ATOM_ESCAPED = -6,  /* a coordinate left [-3L/2, 3L/2) before a wrap */
     MD_ERR_NONFINITE = -7,     /* a coordinate became NaN or infinite */
     MD_ERR_STATE = -8,         /* call not valid in the current state */
@@ -83,7 +86,7 @@ typedef enum {
                             cell counts in Tables 1 and 5); default floor(L / r_n) */
 
 typedef struct {
-    int64_t n_atoms;   /* N >= 1 and N < 2^26 */
+    int64_t n_atoms;   /* 1 <= N < 2^25 */
     double box;        /* edge L of the cube [-L/2, L/2)^3 */
     double r_cut;      /* interaction cutoff r_c; 2^(1/6) selects the soft sphere
                           (shift +1 so u(r_c) = 0); any other value is plain
@@ -92,8 +95,9 @@ typedef struct {
                           the cell-list-only method (re-bin every step) */
     double dt;         /* time step */
     int32_t precision; /* md_precision */
-    int32_t nebr_cap;  /* initial per-atom neighbour capacity; 0 = 48 */
-    int32_t cell_cap;  /* initial per-cell layer capacity; 0 = 16 */
+    int32_t nebr_cap;  /* per-atom neighbour-list capacity; 0 = 48 (atoms with
+                          longer lists are evaluated from the cells) */
+    int32_t cell_cap;  /* initial per-cell layer capacity; 0 = 16 (grown on need) */
     uint32_t flags;    /* MD_EVEN_CELLS */
 } md_params;
 
@@ -108,7 +112,7 @@ typedef struct {
     int64_t n_rebuilds;     /* rebuilds performed by md_step (not counting creation) */
     int64_t step;           /* completed time steps */
     int32_t max_nebr;       /* largest per-atom list length at the last build */
-    int32_t max_cell;       /* largest cell occupancy at the last binning */
+    int32_t max_cell;       /* largest cell occupancy seen by a sort so far */
     int32_t rebuild_due;    /* 1 if the next step starts with a rebuild */
     int32_t cells_per_edge; /* G */
 } md_props_t;
@@ -132,30 +136,35 @@ md_status md_query_bytes(const md_params *p, size_t *bytes);
 
 /* Create a system from host positions and velocities (n x 3 doubles each,
  * any order, positions anywhere in [-3L/2, 3L/2)) and evaluate step 0: wrap,
- * bin, build the neighbour matrix (unless shell == 0), forces, properties,
- * and the first rebuild decision (accumulated displacement = vmax*dt).
- * hip_stream: a hipStream_t, or NULL.  a: allocator, or NULL for hipMalloc.
- * On success *out owns a new system.  Async (the initial copies are staged
- * through host memory owned by the library). */
+ * bin, sort into cell order, build the neighbour matrix (unless shell == 0),
+ * forces, properties, and the first rebuild decision (accumulated
+ * displacement = vmax*dt).  hip_stream: a hipStream_t, or NULL.  a:
+ * allocator, or NULL for hipMalloc.  On success *out owns a new system.
+ * Sync. */
 md_status md_create(const md_params *p, const double *pos, const double *vel,
                     const md_allocator *a, void *hip_stream, md_system **out);
 
 /* Periodic wrap, cell assignment and stable cell-order reordering (cell
- * assignment Sec. 2.2/Code "CellAtomAssign", layer assignment Sec. 2.4,
- * reordering Sec. 2.5): atoms end up stored cell by cell, and within a cell in
- * their previous storage order.  Marks the neighbour matrix stale.  Async. */
+ * assignment Sec. 2.2 and its listing, layer assignment Sec. 2.4, reordering
+ * Sec. 2.5) of the held state: atoms end up stored cell by cell, and within
+ * a cell in their previous storage order.  The new storage order is then
+ * evaluated again (neighbour matrix, forces, properties; the forces can
+ * differ from the previous ones in the last bits, through the summation
+ * order), and the displacement rule restarts from this state.  Sync. */
 md_status md_bin_cells(md_system *s);
 
-/* Build the neighbour matrix W[m][i] (Sec. 2.4): for every atom, all atoms
- * j != i of the 27 surrounding cells with r^2 < r_n^2, visited cell by cell
- * (offsets z-major, x fastest) and in storage order within a cell.  Requires
- * current bins (call md_bin_cells first after md_set_state).  Not available
- * in cell-list-only mode (MD_ERR_STATE).  Async. */
+/* Build the neighbour matrix W[m][i] (Sec. 2.4) at the held state: for
+ * every atom, all atoms j != i of the 27 surrounding cells with r^2 < r_n^2,
+ * visited cell by cell (offsets z-major, x fastest) and in storage order
+ * within a cell.  The list is built from freshly sorted cells, so this also
+ * does what md_bin_cells does.  Not available in cell-list-only mode
+ * (MD_ERR_STATE).  Sync. */
 md_status md_build_nebr(md_system *s);
 
-/* Forces, per-atom energies and virials at the current positions (Sec. 2.4
- * force algorithm; cell method when shell == 0), plus the properties.
- * Stores the forces used by the next md_step.  Async. */
+/* Forces, per-atom energies and virials at the held positions from the
+ * current neighbour matrix (Sec. 2.4 force algorithm; cell method when
+ * shell == 0), plus the properties.  Stores the forces used by the next
+ * md_step.  Sync. */
 md_status md_forces(md_system *s);
 
 /* Advance n_steps leapfrog steps (a)-(e), rebuilding on the device whenever
@@ -176,27 +185,31 @@ md_status md_get_state(md_system *s, double *pos, double *vel, double *force, in
  * original order; either may be NULL.  Sync. */
 md_status md_get_atom_energies(md_system *s, double *u_atom, double *w_atom);
 
-/* Replace positions and velocities (n x 3, original order).  Marks bins and
- * the neighbour matrix stale; the next md_forces / md_step re-bins, rebuilds
- * and re-evaluates forces before integrating.  Async. */
+/* Replace positions and velocities (n x 3, original order) of the held step
+ * and evaluate them as md_create does (wrap, bin, sort, list, forces,
+ * properties); the displacement rule restarts.  Sync. */
 md_status md_set_state(md_system *s, const double *pos, const double *vel);
 
-/* Scalar cell index (c_z*G + c_y)*G + c_x of every atom at the last
- * binning, original order.  Sync. */
+/* Scalar cell index (c_z*G + c_y)*G + c_x of every atom at its last
+ * binning (the held positions, after md_create / md_bin_cells / a step),
+ * original order.  Sync. */
 md_status md_get_cells(md_system *s, int32_t *cell_of_atom);
 
-/* Storage order after the last binning: order[p] = original index of the
- * atom stored at position p; cell_start[c] = first position of cell c,
+/* Storage order after the last sort: order[p] = original index of the atom
+ * stored at position p; cell_start[c] = first position of cell c,
  * cell_start[G^3] = n (either may be NULL).  Sync. */
 md_status md_get_bins(md_system *s, int32_t *order, int32_t *cell_start);
 
 /* Neighbour-matrix entries as ordered pairs (i, j) of original indices, i
  * != j; each unordered pair appears twice (once from each side).  Stores at
- * most cap pairs, *n gets the total.  Sync. */
+ * most cap pairs, *n gets the total.  MD_ERR_NEBR_OVERFLOW if some atom's
+ * list exceeded nebr_cap at the last build.  Sync. */
 md_status md_get_pairs(md_system *s, int64_t cap, int32_t *i, int32_t *j, int64_t *n);
 
-/* Bracket the launches of the force kernel with HIP events from now on
- * (enable != 0), or stop.  md_kernel_time reports launches and the summed
+/* Bracket every launch of the step kernel (forces, list build, integration;
+ * the dominant kernel of a step) with HIP events on the library's stream
+ * from now on (enable != 0), or stop; steps then run as separate launches
+ * instead of graph replays.  md_kernel_time reports launches and the summed
  * event-measured duration since the last enable.  Sync. */
 md_status md_profile(md_system *s, int32_t enable);
 md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms);
@@ -213,13 +226,13 @@ void md_destroy(md_system *s);
  * ------------------------------------------------------------------------- */
 
 /* A batch with room for max_slots systems and hbm_budget bytes of their
- * device state; steps_per_run steps are replayed per md_batch_run. */
+ * device state; steps_per_run (1..64) steps are replayed per md_batch_run. */
 md_status md_batch_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_run,
                           const md_allocator *a, void *hip_stream, md_batch **out);
 
 /* Admit a system that is to advance n_steps steps; evaluates its step 0
  * (as md_create).  MD_ERR_OOM if it does not fit the remaining budget,
- * MD_ERR_NO_SLOT if every slot is busy; the caller retries later.  Async. */
+ * MD_ERR_NO_SLOT if every slot is busy; the caller retries later.  Sync. */
 md_status md_batch_admit(md_batch *b, const md_params *p, const double *pos, const double *vel,
                          int64_t n_steps, int32_t *slot);
 

@@ -14,6 +14,12 @@
 // The cell-layer matrix comes in three sets; the rows of state k live in set
 // k % 3, so one step can read its rows while the next step's rows are
 // written and the set after that is cleared.
+//
+// Storage order: the atoms are stored in cell order as of the last rebuild.
+// A rebuild step sorts r(k) by cell (stable counting sort from the rows of
+// set k % 3) into the other descriptor variant, so the atoms of a cell are
+// contiguous and cell_start gives their range.  CtlDev::var_ring[k % 3] is
+// the variant that holds state k.
 #pragma once
 
 #include <stdint.h>
@@ -21,9 +27,21 @@
 namespace md {
 
 constexpr int TILE = 256;          // atoms per tile (one workgroup of 4 wave64)
-constexpr int CTILE = 2048;        // cells per scan tile (8 per thread)
-constexpr int J_BITS = 26;         // neighbour entry: index in the low 26 bits
-constexpr int32_t J_MASK = (1 << J_BITS) - 1;
+constexpr int CTILE = 256;         // cells per sort tile (one per thread)
+// Neighbour entry (32 bits): bits 0-24 an index, bit 25 (GFLAG) set when the
+// index is a storage index and clear when it is a slot of the tile's LDS
+// window, bits 26-31 the periodic image code (2 bits per dimension).
+constexpr int J_BITS = 26;         // image code starts here
+constexpr int IDX_BITS = 25;
+constexpr uint32_t IDX_MASK = (1u << IDX_BITS) - 1;
+constexpr uint32_t GFLAG = 1u << IDX_BITS;
+// LDS window of a tile: the storage-index intervals holding every candidate
+// neighbour of the tile's atoms at the last sort, staged into LDS each step.
+constexpr int WCAP = 1640;         // atoms (FP64 x, y, z: 38.4 KB, four workgroups per CU)
+constexpr int NROWS = 64;          // (source row, dz, dy) combinations a window describes
+constexpr int NOSLOT = INT32_MIN;  // storage-index-to-slot offset of a piece not in LDS
+constexpr int NWIN = 32;           // intervals
+constexpr int WSTRIDE = 1 + 3 * NWIN;  // ints per tile: count, then (start, len, slot)
 constexpr int NPART = 8;           // doubles per tile in the property partials
 constexpr int MAX_GRID = 2048;     // persistent-style grid bound (256 CUs x 8)
 constexpr int OVF_CAP = 4096;      // per-set overflow list of cell-layer rows
@@ -34,35 +52,36 @@ enum : int32_t {
   ERR_CELL = 2,       // a cell-layer set overflowed beyond its overflow list (repairable)
   ERR_ESCAPED = 4,    // a coordinate outside [-3L/2, 3L/2) when binned
   ERR_NONFINITE = 8,  // NaN / Inf coordinate
-  ERR_SCAN = 16,      // scan look-back gave up (safety net)
 };
 
-// Modes of the step kernel.
+// Modes of the step kernel (and of the sort kernel: MODE_STEP or not).
 enum : int32_t {
   MODE_STEP = 0,    // forces (c) + (d) + (e) [+ (a) of the next step and its binning]
   MODE_FORCES = 1,  // force evaluation at a clean state: store F, u_i, w_i, partials
   MODE_BUILD = 2,   // neighbour matrix only, at a clean state
 };
 
-// Per-replica device descriptor: read-only while kernels run (the host swaps
-// the *_alt buffers after a reordering and uploads the descriptor again).
+// Per-replica device descriptor, read-only while kernels run.  The two
+// variants of a replica differ in the sorted arrays: variant 1 swaps the two
+// time-level buffers of P and V, and id with id_alt, cell with cell_alt.  A
+// sort gathers the current time level into the other variant's buffers,
+// which hold a time level nobody reads any more.
 struct SlotDev {
   double *P[2][3];                  // positions x, y, z; two time-level buffers
   double *V[2][3];                  // velocities; two time-level buffers
   int32_t *id, *id_alt;             // original atom index of each storage position
-  void *F, *F_alt;                  // forces, SoA [3][npad] of float or double
-  void *UA, *UA_alt;                // per-atom u then w, [2][npad] of float or double
   int32_t *cell, *cell_alt;         // cell of each atom at its latest binning
-  int32_t *m, *m_alt;               // neighbour-list length per atom
-  int32_t *W, *W_alt;               // neighbour matrix [mcap][npad]
+  void *F;                          // forces, SoA [3][npad] of float or double
+  void *UA;                         // per-atom u then w, [2][npad] of float or double
+  int32_t *m;                       // neighbour-list length per atom
+  int32_t *W;                       // neighbour matrix [mcap][npad]
   int32_t *cnt[3];                  // per set: occupancy of every cell
+  int32_t *tcnt[3];                 // per set: occupancy of every cell tile (CTILE cells)
   int32_t *H[3];                    // per set: cell-layer rows [ncell][hcap]
   int32_t *ovf[3];                  // per set: (cell, atom) pairs beyond hcap
   int32_t *ovf_n;                   // [3] fill of the overflow lists
-  int32_t *cs;                      // cell_start[ncell + 1] of the last reordering scan
-  int32_t *perm;                    // reordering: old index of new position p
-  int32_t *inv;                     // reordering: new position of old index a
-  unsigned long long *scan_st;      // scan look-back status per cell tile
+  int32_t *cs;                      // cell_start[ncell + 1] of the last sort
+  int32_t *win;                     // per atom tile: LDS window [WSTRIDE] (count < 0: none)
   double *part;                     // per-tile partial properties [ntiles][NPART]
   unsigned long long *vring;        // max v^2 of step k: [k % 3][VSPREAD] slots, 16 words apart
   double L, halfL, invW, rn2, rc2, dt, hdt, half_shell, ushift, pad0;
@@ -87,9 +106,11 @@ struct CtlDev {
   uint64_t vmax_ring[3];  // max v(k)^2 of ring entry k % 3, gathered by k_props (host view)
   double disp_ring[3];    // accumulated displacement after step k, slot k % 3
   int32_t clean;       // 1: r(done), v(done), F(done) are held; 0: drifted to r(done+1)
-  int32_t variant;     // which of the two descriptors of the replica is current
+  int32_t var_ring[3]; // descriptor variant holding state k, slot k % 3
+  int32_t rb_ring[3];  // 1 if step k rebuilds (decided by k_sort of step k), slot k % 3
   int32_t err;         // latched ERR_* bits
-  int32_t max_h;       // largest cell occupancy seen by a reordering scan
+  int32_t max_h;       // largest cell occupancy seen by a sort
+  int32_t pad1;
   // properties reduced by k_props
   double ke, pe, vir, vmax2;
   int64_t sum_m;
@@ -97,11 +118,10 @@ struct CtlDev {
 };
 
 // Engine-wide header (device int32[8]).
-enum { HDR_NTILES = 0, HDR_NCTILES = 1, HDR_TICKET = 2 };
+enum { HDR_NTILES = 0, HDR_NCTILES = 1 };
 
-// Each replica has two descriptors: the second swaps every double-buffered
-// array (the positions/velocities buffer pair and each array with its _alt).
-// A reordering gathers into the other buffers and flips CtlDev::variant.
+// Each replica has two descriptors (see SlotDev); CtlDev::var_ring says
+// which one holds a given state.
 struct Tables {
   const SlotDev *slots;       // [2 * nslots]: descriptor variant v of replica r at 2 r + v
   CtlDev *ctl;

@@ -5,12 +5,10 @@
 // with one replica; md_batch is an engine with many slots.
 //
 // Steps are replayed from captured HIP graphs of K steps (K a power of two up
-// to 64): K launches of the step kernel and one counter update.  Graph
-// boundaries fall on multiples of 64 in each replica's step count, and at
-// those boundaries the replicas that are mid-run are reordered into cell
-// order (a relabeling that leaves every force sum unchanged).  All kernel
-// arguments are pointers to device tables, so graphs stay valid when slots
-// are admitted or released.
+// to 64): per step a launch of the sort kernel (which does work only where
+// the rebuild rule fires) and one of the step kernel, then one counter
+// update.  All kernel arguments are pointers to device tables, so graphs stay
+// valid when slots are admitted or released.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,7 +30,7 @@ namespace {
 
 constexpr int DEFAULT_MCAP = 48;
 constexpr int DEFAULT_HCAP = 16;
-constexpr int GRAPH_CHUNK = 64;      // steps per replay graph; reordering period
+constexpr int GRAPH_CHUNK = 64;      // steps per replay graph (largest)
 constexpr int PROFILE_SETS = 2;      // ping-pong event sets when profiling
 
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -46,7 +44,7 @@ struct Geometry {
 
 md_status geometry(const md_params *p, Geometry *g) {
   if (!p || !g) return MD_ERR_INVALID_ARG;
-  if (p->n_atoms <= 0 || p->n_atoms >= (int64_t(1) << J_BITS)) return MD_ERR_INVALID_ARG;
+  if (p->n_atoms <= 0 || p->n_atoms > (int64_t)IDX_MASK) return MD_ERR_INVALID_ARG;
   if (!(p->box > 0) || !(p->dt > 0) || !(p->r_cut > 0) || !(p->shell >= 0))
     return MD_ERR_INVALID_ARG;
   if (!std::isfinite(p->box) || !std::isfinite(p->dt) || !std::isfinite(p->r_cut) ||
@@ -80,8 +78,11 @@ md_status geometry(const md_params *p, Geometry *g) {
 
 // Layout of the per-replica state block (everything but H and W), in order.
 struct Layout {
-  size_t pv, ids, fu, cellm, perm, cnt, cs, ovf, scan, part, vring, total;
+  size_t pv, ids, fu, cellm, cnt, tcnt, cs, win, ovf, part, vring, total;
 };
+// Bytes of one set's cell counters (cnt) and tile counters (tcnt).
+size_t cnt_set_bytes(const Geometry &g) { return round_up((size_t)g.nctiles * CTILE * 4, 256); }
+size_t tcnt_set_bytes(const Geometry &g) { return round_up((size_t)g.nctiles * 4, 256); }
 Layout layout(const Geometry &g) {
   const size_t R = g.fp64 ? 8 : 4, np = g.npad;
   const size_t cells = (size_t)g.nctiles * CTILE;
@@ -92,19 +93,19 @@ Layout layout(const Geometry &g) {
   l.ids = b;
   b += round_up(2 * np * 4, 256);           // id, id_alt
   l.fu = b;
-  b += round_up(10 * np * R, 256);          // F, F_alt, UA, UA_alt
+  b += round_up(5 * np * R, 256);           // F[3], UA[2]
   l.cellm = b;
-  b += round_up(4 * np * 4, 256);           // cell, cell_alt, m, m_alt
-  l.perm = b;
-  b += round_up(2 * np * 4, 256);           // perm, inv
+  b += round_up(3 * np * 4, 256);           // cell, cell_alt, m
   l.cnt = b;
-  b += 3 * round_up(cells * 4, 256);        // cnt[3]
+  b += 3 * cnt_set_bytes(g);                // cnt[3]
+  l.tcnt = b;
+  b += 3 * tcnt_set_bytes(g);               // tcnt[3]
   l.cs = b;
   b += round_up(cells * 4, 256);            // cell_start
+  l.win = b;
+  b += round_up((size_t)g.ntiles * WSTRIDE * 4, 256);  // LDS windows of the tiles
   l.ovf = b;
   b += round_up(3 * 2 * OVF_CAP * 4 + 3 * 4, 256);  // ovf[3], ovf_n[3]
-  l.scan = b;
-  b += round_up((size_t)g.nctiles * 8, 256);
   l.part = b;
   b += round_up((size_t)g.ntiles * NPART * 8, 256);
   l.vring = b;
@@ -115,7 +116,7 @@ Layout layout(const Geometry &g) {
 size_t h_bytes(const Geometry &g, int hcap) {
   return 3 * round_up((size_t)g.ncell * hcap * 4, 256);
 }
-size_t w_bytes(const Geometry &g, int mcap) { return 2 * round_up((size_t)mcap * g.npad * 4, 256); }
+size_t w_bytes(const Geometry &g, int mcap) { return round_up((size_t)mcap * g.npad * 4, 256); }
 size_t total_bytes(const Geometry &g) {
   return layout(g).total + h_bytes(g, g.hcap) + (g.mcap ? w_bytes(g, g.mcap) : 0);
 }
@@ -153,7 +154,6 @@ struct Engine {
   bool verbose = getenv("MD_VERBOSE") != nullptr;
   size_t budget = 0, used = 0;
   int steps_per_run = GRAPH_CHUNK;
-  unsigned scan_epoch = 1;
   int64_t host_target = 0;      // single system: target of the last md_step
   int prec = 0;                 // PREC_* bits of the admitted replicas (step-kernel variants)
   // profiling of the step kernel (eager launches bracketed by events: events
@@ -287,12 +287,12 @@ void engine_free(Engine *e) {
 }
 
 // Fill both descriptor variants of a replica from its allocations.  Variant 1
-// swaps every buffer pair of variant 0.
+// swaps the time-level buffers of P and V, id with id_alt and cell with
+// cell_alt.
 void describe(Replica *r) {
   const Geometry &g = r->g;
   const Layout l = layout(g);
   const size_t np = g.npad, R = g.fp64 ? 8 : 4;
-  const size_t cells = (size_t)g.nctiles * CTILE;
   char *b = (char *)r->state;
   SlotDev d{};
   double *pv = (double *)(b + l.pv);
@@ -304,27 +304,22 @@ void describe(Replica *r) {
   d.id = (int32_t *)(b + l.ids);
   d.id_alt = d.id + np;
   d.F = b + l.fu;
-  d.F_alt = b + l.fu + 3 * np * R;
-  d.UA = b + l.fu + 6 * np * R;
-  d.UA_alt = b + l.fu + 8 * np * R;
+  d.UA = b + l.fu + 3 * np * R;
   d.cell = (int32_t *)(b + l.cellm);
   d.cell_alt = d.cell + np;
   d.m = d.cell + 2 * np;
-  d.m_alt = d.cell + 3 * np;
-  d.perm = (int32_t *)(b + l.perm);
-  d.inv = d.perm + np;
   for (int s = 0; s < 3; ++s) {
-    d.cnt[s] = (int32_t *)(b + l.cnt + s * round_up(cells * 4, 256));
+    d.cnt[s] = (int32_t *)(b + l.cnt + s * cnt_set_bytes(g));
+    d.tcnt[s] = (int32_t *)(b + l.tcnt + s * tcnt_set_bytes(g));
     d.H[s] = (int32_t *)((char *)r->hmat + s * round_up((size_t)g.ncell * g.hcap * 4, 256));
     d.ovf[s] = (int32_t *)(b + l.ovf) + s * 2 * OVF_CAP;
   }
   d.ovf_n = (int32_t *)(b + l.ovf) + 3 * 2 * OVF_CAP;
   d.cs = (int32_t *)(b + l.cs);
-  d.scan_st = (unsigned long long *)(b + l.scan);
+  d.win = (int32_t *)(b + l.win);
   d.part = (double *)(b + l.part);
   d.vring = (unsigned long long *)(b + l.vring);
   d.W = (int32_t *)r->wmat;
-  d.W_alt = r->wmat ? (int32_t *)((char *)r->wmat + w_bytes(g, g.mcap) / 2) : nullptr;
   d.L = g.L;
   d.halfL = 0.5 * g.L;
   d.invW = (double)g.G / g.L;
@@ -351,11 +346,7 @@ void describe(Replica *r) {
     std::swap(e.V[0][a], e.V[1][a]);
   }
   std::swap(e.id, e.id_alt);
-  std::swap(e.F, e.F_alt);
-  std::swap(e.UA, e.UA_alt);
   std::swap(e.cell, e.cell_alt);
-  std::swap(e.m, e.m_alt);
-  std::swap(e.W, e.W_alt);
   const int32_t to = r->dev[0].tile_off, co = r->dev[0].ctile_off;
   r->dev[0] = d;
   r->dev[1] = e;
@@ -448,7 +439,6 @@ md_status status_of(int err) {
   if (err & ERR_NONFINITE) return MD_ERR_NONFINITE;
   if (err & ERR_ESCAPED) return MD_ERR_ATOM_ESCAPED;
   if (err & ERR_CELL) return MD_ERR_CELL_OVERFLOW;
-  if (err & ERR_SCAN) return MD_ERR_STATE;
   return MD_OK;
 }
 
@@ -458,26 +448,26 @@ md_status first_error(Engine *e, int only = -1) {
   return MD_OK;
 }
 
-// Reorder the held state of the replicas into cell order (all, or `only`):
-// scan + ranks + gather into the alternate buffers, switch buffers, and bin
-// the held state again under its new indices.
-md_status reorder(Engine *e, int only) {
-  Tables T = e->tables();
-  launch_reorder(T, e->grid, e->cgrid, e->scan_epoch++, only, e->work);
-  launch_flip(T, only, e->work);
-  launch_clear_set(T, e->cgrid, only, e->work);
-  launch_insert(T, e->grid, 0, only, e->work);
-  return e->check("reorder launches");
-}
-
-// Wrap, bin, reorder and evaluate the held clean state of the replicas (all
-// or `only`): the creation-time evaluation (step 0's (b)-(e)), also used
-// after md_set_state.
-md_status evaluate_clean(Engine *e, int only, int mode, int force_build) {
+// Wrap, bin and sort the held clean state of the replicas (all, or `only`)
+// into cell order, and bin it again under its new indices (the rows then
+// serve an atom whose neighbour list overflows).
+md_status host_sort(Engine *e, int only) {
   Tables T = e->tables();
   launch_clear_set(T, e->cgrid, only, e->work);
   launch_insert(T, e->grid, 1, only, e->work);
-  md_status st = reorder(e, only);
+  launch_sort(T, e->cgrid, 0, MODE_FORCES, only, e->work);
+  launch_flip(T, only, e->work);
+  launch_clear_set(T, e->cgrid, only, e->work);
+  launch_insert(T, e->grid, 0, only, e->work);
+  return e->check("sort launches");
+}
+
+// Sort and evaluate the held clean state of the replicas (all or `only`):
+// the creation-time evaluation (step 0's (b)-(e)), also used after
+// md_set_state and by md_bin_cells / md_build_nebr.
+md_status evaluate_clean(Engine *e, int only, int mode, int force_build) {
+  Tables T = e->tables();
+  md_status st = host_sort(e, only);
   if (st != MD_OK) return st;
   launch_step(T, e->grid, 0, mode, force_build, only, e->prec, e->work);
   launch_props(T, only, e->work);
@@ -570,9 +560,19 @@ void reset_ctl(CtlDev &c, int64_t step, int variant, int64_t n_rebuilds, int max
   c.err_step = INT64_MAX;
   c.n_rebuilds = n_rebuilds;
   c.clean = 1;
-  c.variant = variant;
+  for (int q = 0; q < 3; ++q) c.var_ring[q] = variant;
   c.max_h = max_h;
 }
+
+// Clear the three cell-layer sets of a replica (counters and overflow fill).
+hipError_t clear_sets(Engine *e, Replica *r) {
+  const Layout l = layout(r->g);
+  hipError_t err = hipMemsetAsync((char *)r->state + l.cnt, 0, l.cs - l.cnt, e->work);
+  if (err == hipSuccess) err = hipMemsetAsync(r->dev[0].ovf_n, 0, 3 * 4, e->work);
+  return err;
+}
+
+int held_variant(const CtlDev &c) { return c.var_ring[((c.done % 3) + 3) % 3] & 1; }
 
 // Enlarge the cell-layer matrix of slot s after ERR_CELL and bin its held
 // state again (the state itself is intact: the overflowing binning was the
@@ -593,12 +593,7 @@ md_status repair_cells(Engine *e, int s) {
   r->g.hcap = hcap;
   describe(r);
   // all three sets start empty again (the counters live in the state block)
-  for (int q = 0; q < 3; ++q) {
-    err = hipMemsetAsync(r->dev[0].cnt[q], 0, (size_t)r->g.nctiles * CTILE * 4, e->work);
-    if (err != hipSuccess) return e->fail("regrow", err);
-  }
-  err = hipMemsetAsync(r->dev[0].ovf_n, 0, 3 * 4, e->work);
-  if (err != hipSuccess) return e->fail("regrow", err);
+  if ((err = clear_sets(e, r)) != hipSuccess) return e->fail("regrow", err);
   c.err &= ~ERR_CELL;
   c.err_step = INT64_MAX;
   md_status st = upload_tables(e);
@@ -620,7 +615,10 @@ hipGraphExec_t step_graph(Engine *e, int k) {
     e->fail("begin capture", err);
     return nullptr;
   }
-  for (int s = 0; s < k; ++s) launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work);
+  for (int s = 0; s < k; ++s) {
+    launch_sort(T, e->cgrid, s, MODE_STEP, -1, e->work);
+    launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work);
+  }
   launch_replay_end(T, k, e->work);
   err = hipStreamEndCapture(e->work, &g);
   if (err == hipSuccess) err = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
@@ -657,6 +655,7 @@ md_status replay(Engine *e, int k) {
     if (st != MD_OK) return st;
     Tables T = e->tables();
     for (int s = 0; s < k; ++s) {
+      launch_sort(T, e->cgrid, s, MODE_STEP, -1, e->work);
       hipError_t err = hipEventRecord(e->prof_ev[set][s][0], e->work);
       launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work);
       if (err == hipSuccess) err = hipEventRecord(e->prof_ev[set][s][1], e->work);
@@ -672,21 +671,16 @@ md_status replay(Engine *e, int k) {
   return err == hipSuccess ? MD_OK : e->fail("graph launch", err);
 }
 
-// Advance a single system from absolute step `from` to `to`: replays end on
-// multiples of GRAPH_CHUNK, where the (still running) system is reordered.
+// Advance a single system from absolute step `from` to `to` in replays of
+// GRAPH_CHUNK steps and a power-of-two decomposition of the rest.
 md_status run_steps(Engine *e, int64_t from, int64_t to) {
   int64_t pos = from;
   while (pos < to) {
-    const int64_t room = GRAPH_CHUNK - (pos % GRAPH_CHUNK);
-    const int64_t c = std::min<int64_t>(room, to - pos);
     int k = GRAPH_CHUNK;
-    while (k > c) k >>= 1;
+    while (k > to - pos) k >>= 1;
     md_status st = replay(e, k);
     if (st != MD_OK) return st;
     pos += k;
-    if (pos % GRAPH_CHUNK == 0 && pos < to) {
-      if ((st = reorder(e, -1)) != MD_OK) return st;
-    }
   }
   return MD_OK;
 }
@@ -719,7 +713,7 @@ md_status fetch(Engine *e, int s, double *pos, double *vel, double *force, doubl
                 double *w_atom, int32_t *cell_of_atom) {
   Replica *r = e->rep[s];
   const CtlDev &c = e->h_ctl[s];
-  const SlotDev &d = r->dev[c.variant & 1];
+  const SlotDev &d = r->dev[held_variant(c)];
   const int64_t n = r->g.n, np = r->g.npad;
   const size_t R = r->g.fp64 ? 8 : 4;
   const int64_t k = c.clean ? c.done : c.done + 1;
@@ -919,14 +913,9 @@ md_status md_bin_cells(md_system *s) {
   Engine *e = s->e;
   if ((st = e->enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
-  // wrap + bin the held state, reorder, rebuild the list at these positions
-  Tables T = e->tables();
-  launch_clear_set(T, e->cgrid, -1, e->work);
-  launch_insert(T, e->grid, 1, -1, e->work);
-  if ((st = reorder(e, -1)) != MD_OK) return st;
-  if (!e->rep[0]->g.cell_only) launch_step(T, e->grid, 0, MODE_BUILD, 1, -1, e->prec, e->work);
-  if ((st = e->check("bin launches")) != MD_OK) return st;
-  if ((st = sync_system(e)) != MD_OK) return st;
+  // wrap + bin + sort the held state; the new storage order invalidates the
+  // list and the stored forces, so both are evaluated again
+  if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
   if ((st = set_force_step(e, 0)) != MD_OK) return st;
   return e->leave();
 }
@@ -938,8 +927,8 @@ md_status md_build_nebr(md_system *s) {
   if (e->rep[0]->g.cell_only) return MD_ERR_STATE;
   if ((st = e->enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
-  launch_step(e->tables(), e->grid, 0, MODE_BUILD, 1, -1, e->prec, e->work);
-  if ((st = sync_system(e)) != MD_OK) return st;
+  // the list is built from the contiguous cell ranges of freshly sorted atoms
+  if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
   if ((st = set_force_step(e, 0)) != MD_OK) return st;
   return e->leave();
 }
@@ -968,10 +957,6 @@ md_status md_step(md_system *s, int64_t n_steps) {
   launch_set_target(T, 0, to, e->work);
   launch_kick(T, e->grid, e->work);
   if ((st = e->check("kick")) != MD_OK) return st;
-  // a run that passes a multiple of the period reorders there, in the
-  // drifted state; a call that starts on one does the same after its kick,
-  // so the storage order never depends on how the steps were split into calls
-  if (from > 0 && from % GRAPH_CHUNK == 0 && (st = reorder(e, -1)) != MD_OK) return st;
   if ((st = run_steps(e, from, to)) != MD_OK) return st;
   e->host_target = to;
   return e->leave();
@@ -1022,15 +1007,11 @@ md_status md_set_state(md_system *s, const double *pos, const double *vel) {
   Replica *r = e->rep[0];
   CtlDev &c = e->h_ctl[0];
   const int64_t step = c.clean ? c.done : c.done + 1;
-  const int variant = c.variant & 1;
+  const int variant = held_variant(c);
   if ((st = upload_state(e, r, variant, step, pos, vel)) != MD_OK) return st;
   reset_ctl(c, step, variant, c.n_rebuilds, c.max_h);
   if ((st = write_ctl(e, 0)) != MD_OK) return st;
-  for (int q = 0; q < 3; ++q)
-    if (hipMemsetAsync(r->dev[0].cnt[q], 0, (size_t)r->g.nctiles * CTILE * 4, e->work) !=
-        hipSuccess)
-      return e->fail("clear sets");
-  if (hipMemsetAsync(r->dev[0].ovf_n, 0, 12, e->work) != hipSuccess) return e->fail("clear sets");
+  if (clear_sets(e, r) != hipSuccess) return e->fail("clear sets");
   if (hipMemsetAsync(r->dev[0].vring, 0, 3 * VSPREAD * 16 * 8, e->work) != hipSuccess)
     return e->fail("clear ring");
   e->host_target = step;
@@ -1057,7 +1038,7 @@ md_status md_get_bins(md_system *s, int32_t *order, int32_t *cell_start) {
   if ((st = e->enter()) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
   Replica *r = e->rep[0];
-  const SlotDev &d = r->dev[e->h_ctl[0].variant & 1];
+  const SlotDev &d = r->dev[held_variant(e->h_ctl[0])];
   hipError_t err = hipSuccess;
   if (order) err = hipMemcpyAsync(order, d.id, (size_t)r->g.n * 4, hipMemcpyDeviceToHost, e->work);
   if (err == hipSuccess && cell_start)
@@ -1077,22 +1058,35 @@ md_status md_get_pairs(md_system *s, int64_t cap, int32_t *pi, int32_t *pj, int6
   if (r->g.cell_only) return MD_ERR_STATE;
   if ((st = e->enter()) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
-  const SlotDev &d = r->dev[e->h_ctl[0].variant & 1];
+  const SlotDev &d = r->dev[held_variant(e->h_ctl[0])];
   const int64_t n = r->g.n;
   const size_t np = r->g.npad;
-  std::vector<int32_t> W((size_t)r->g.mcap * np), m(n), id(n);
+  std::vector<int32_t> W((size_t)r->g.mcap * np), m(n), id(n),
+      win((size_t)r->g.ntiles * WSTRIDE);
   hipError_t err = hipMemcpyAsync(W.data(), d.W, W.size() * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(win.data(), d.win, win.size() * 4, hipMemcpyDeviceToHost, e->work);
   if (err == hipSuccess)
     err = hipMemcpyAsync(m.data(), d.m, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
   if (err == hipSuccess)
     err = hipMemcpyAsync(id.data(), d.id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
   if (err == hipSuccess) err = hipStreamSynchronize(e->work);
   if (err != hipSuccess) return e->fail("get pairs", err);
+  // an entry is a storage index (GFLAG) or a slot of the tile's LDS window
+  auto storage_index = [&](int64_t p, uint32_t e) -> int64_t {
+    const int64_t idx = e & IDX_MASK;
+    if (e & GFLAG) return idx;
+    const int32_t *wt = &win[(size_t)(p / TILE) * WSTRIDE];
+    for (int q = 0; q < wt[0]; ++q)
+      if (idx >= wt[3 * q + 3] && idx < wt[3 * q + 3] + wt[3 * q + 2])
+        return wt[3 * q + 1] + (idx - wt[3 * q + 3]);
+    return -1;
+  };
   int64_t k = 0;
   for (int64_t p = 0; p < n; ++p) {
     if (m[p] > r->g.mcap) return MD_ERR_NEBR_OVERFLOW;  // list incomplete for this atom
     for (int q = 0; q < m[p]; ++q) {
-      const int j = W[(size_t)q * np + p] & J_MASK;
+      const int64_t j = storage_index(p, (uint32_t)W[(size_t)q * np + p]);
       if (k < cap) {
         pi[k] = id[p];
         pj[k] = (j >= 0 && j < n) ? id[j] : -1;
@@ -1153,8 +1147,7 @@ void md_destroy(md_system *s) {
 md_status md_batch_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_run,
                           const md_allocator *a, void *hip_stream, md_batch **out) {
   if (!out || max_slots <= 0 || steps_per_run <= 0) return MD_ERR_INVALID_ARG;
-  // runs end on multiples of the reordering period in every replica's step count
-  if (steps_per_run > GRAPH_CHUNK || (GRAPH_CHUNK % steps_per_run) != 0) return MD_ERR_INVALID_ARG;
+  if (steps_per_run > GRAPH_CHUNK) return MD_ERR_INVALID_ARG;
   *out = nullptr;
   Engine *e = new (std::nothrow) Engine();
   if (!e) return MD_ERR_OOM;
@@ -1242,8 +1235,6 @@ md_status md_batch_run(md_batch *b) {
   launch_kick(e->tables(), e->grid, e->work);
   if ((st = e->check("kick")) != MD_OK) return st;
   if ((st = replay(e, e->steps_per_run)) != MD_OK) return st;
-  // every replica's step count is a multiple of the period after a full run
-  if (e->steps_per_run == GRAPH_CHUNK && (st = reorder(e, -1)) != MD_OK) return st;
   return e->leave();
 }
 

@@ -24,10 +24,12 @@ void launch_set_target(const Tables &T, int slot, long long target, hipStream_t 
 void launch_props(const Tables &T, int only, hipStream_t s);
 // Bin the held state into its cell-layer set (optionally wrapping in place).
 void launch_insert(const Tables &T, int grid, int wrap_store, int only, hipStream_t s);
-// Reordering into cell order: scan, ranks, gather into the alternate buffers.
-void launch_reorder(const Tables &T, int grid, int cgrid, unsigned epoch, int only,
-                    hipStream_t s);
-// Make the alternate buffers current.
+// Counting sort by cell into the other buffer variant: in a step
+// (MODE_STEP, step index s of the replay; only where the rebuild rule fires)
+// or of the held clean state (any other mode; follow with launch_flip).
+void launch_sort(const Tables &T, int cgrid, int step_in_replay, int mode, int only,
+                 hipStream_t s);
+// After a sort of the held states: make the sorted variant current.
 void launch_flip(const Tables &T, int only, hipStream_t s);
 // Clear the held state's cell-layer set.
 void launch_clear_set(const Tables &T, int cgrid, int only, hipStream_t s);

@@ -1,24 +1,24 @@
 // md_kernels.hip -- gfx950 kernels of the soft-sphere MD hot path.
 //
-// One time step of every replica of an engine is ONE launch of k_step:
-//   (b) when the displacement rule fires (or always with the plain cell
-//       method): wrap, and build the neighbour matrix W from the cell-layer
-//       rows of the current positions;
-//   (c) forces from W (or from the rows);
-//   (d), (e) second half kick, kinetic energy, maximum speed;
-//   (a) of the next step: half kick and drift, and the binning of the new
-//       positions into the next cell-layer set (cell + layer assignment).
-// Nothing in k_step waits for other workgroups: the rebuild decision of step
-// k is recomputed by every workgroup from the maximum speed of step k-1
-// (one atomicMax per wave into a ring slot) and the displacement committed
-// by step k-1, so no device-scope fence or "last block" finalisation is
-// needed (on gfx950 a device-scope release writes back the whole L2).
-//
-// Reordering into cell order (Sec. 2.5) is a relabeling done between graph
-// replays: scan of the cell occupancy (k_scan), stable in-cell ranks
-// (k_rank), and a gather of every per-atom array with the neighbour indices
-// remapped (k_permute).  Properties are reduced on demand (k_props) in a
-// fixed order.
+// One time step k of every replica of an engine is two launches:
+//   k_sort  (b) when the displacement rule fires (always with the plain cell
+//           method): wrap, and a stable counting sort of the atoms by cell
+//           (Secs. 2.4, 2.5) -- cell_start from the occupancy counts, ranks
+//           from the cell-layer rows, scatter into the other buffer variant.
+//           Replicas that do not rebuild leave at once.
+//   k_step  (b) the neighbour matrix W from the contiguous cell ranges of
+//           the sorted atoms when rebuilding; (c) forces from W (or from the
+//           cells); (d), (e) second half kick, kinetic energy, maximum speed;
+//           (a) of the next step: half kick and drift, and the binning of the
+//           new positions into the next cell-layer set.
+// Nothing waits for other workgroups inside a launch: the rebuild decision of
+// step k is recomputed by every workgroup of k_sort from the maximum speed of
+// step k-1 (one atomicMax per workgroup into a spread ring slot) and the
+// displacement committed by step k-1, and committed for k_step by the
+// workgroup of the replica's first cell tile, so no device-scope fence or
+// "last block" finalisation is needed (on gfx950 a device-scope release writes
+// back the whole L2).  Properties are reduced on demand (k_props) in a fixed
+// order.
 //
 // Floating point: compiled with -ffp-contract=off, so every FP64 expression
 // rounds as written (no fused multiply-add); cell indices and neighbour
@@ -36,6 +36,15 @@ namespace md {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+
+// Global-address-space view of a pointer read from a descriptor: the loads
+// and stores through it are global_* instructions instead of flat_* ones
+// (which also count against the LDS wait counter).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gp(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+typedef const __attribute__((address_space(1))) double *gcdouble;
 
 // Workgroups go to the 8 XCDs round-robin; renumber them so that each XCD
 // walks a contiguous range of tiles and neighbouring atoms share an L2.
@@ -55,6 +64,29 @@ __device__ __forceinline__ double wave_max(double v) {
 __device__ __forceinline__ int wave_max_i(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
+}
+
+// Maximum over the wave of a 64-bit unsigned value, in every lane: DPP row
+// shifts within rows of 16 lanes, then row broadcasts (ALU only, no LDS
+// round trips); lanes that have no source keep their own value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_max_step(unsigned long long v) {
+  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  const uint32_t slo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+  const uint32_t shi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+  const unsigned long long o = ((unsigned long long)shi << 32) | slo;
+  return o > v ? o : v;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  v = dpp_max_step<0x111, 0xF>(v);  // row_shr:1
+  v = dpp_max_step<0x112, 0xF>(v);  // row_shr:2
+  v = dpp_max_step<0x114, 0xF>(v);  // row_shr:4
+  v = dpp_max_step<0x118, 0xF>(v);  // row_shr:8: lane 15 of a row holds the row maximum
+  v = dpp_max_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_max_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3: lane 63 holds all
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // Compensated FP32 pair (value, error) and exact TwoSum combination.
@@ -97,17 +129,16 @@ __device__ __forceinline__ int cell_of(const SlotDev &S, double x, double y, dou
          cell_coord(x, S.halfL, S.invW, G);
 }
 
-__device__ __forceinline__ const SlotDev &slot_of(const Tables &T, int r) {
-  return T.slots[2 * r + T.ctl[r].variant];
+// Descriptor of the state a replica holds between launches (r(done), or the
+// drifted r(done+1), which lives in the same variant).
+__device__ __forceinline__ const SlotDev &slot_held(const Tables &T, int r) {
+  const CtlDev &C = T.ctl[r];
+  return T.slots[2 * r + C.var_ring[mod3(C.done)]];
 }
 
-// State index held by a replica between launches, and where v lives.
+// State index held by a replica between launches.
 __device__ __forceinline__ int64_t cur_state(const CtlDev &C) {
   return C.clean ? C.done : C.done + 1;
-}
-__device__ __forceinline__ int vbuf_of(const CtlDev &C) {
-  const int64_t k = cur_state(C);
-  return (int)((C.clean ? k + 1 : k) & 1);
 }
 
 __device__ __forceinline__ void latch_error(CtlDev &C, int bits, int64_t step) {
@@ -130,7 +161,7 @@ __device__ void bin_atom(const SlotDev &S, CtlDev &C, int set, int i, double x, 
   }
   if (bad) latch_error(C, bad, step);
   const int c = cell_of(S, wrap1(x, S.L, S.halfL), wrap1(y, S.L, S.halfL), wrap1(z, S.L, S.halfL));
-  S.cell[i] = c;
+  gp(S.cell)[i] = c;
   // Consecutive lanes with the same cell take their layer slots with one
   // atomic: atoms are stored in cell order, so most of a cell's atoms are
   // neighbours in a wave.
@@ -147,8 +178,18 @@ __device__ void bin_atom(const SlotDev &S, CtlDev &C, int set, int i, double x, 
   int base = 0;
   if (leader) base = atomicAdd(&S.cnt[set][c], next - lane);
   const int slot = __shfl(base, lead, 64) + (lane - lead);
+  // the occupancy of the cell's tile, one atomic per run of lanes in one tile
+  // (the shuffle runs on every active lane: a lane reading from an inactive
+  // one gets 0)
+  const int ct = c / CTILE;
+  const int ctp = __shfl_up(ct, 1, 64);
+  const bool tlead = lane == 0 || ctp != ct;
+  const unsigned long long tmask = __ballot(tlead) & active;
+  const unsigned long long tafter = tmask & ~upto;
+  const int tnext = tafter ? __ffsll((long long)tafter) - 1 : na;
+  if (tlead) atomicAdd(&S.tcnt[set][ct], tnext - lane);
   if (slot < S.hcap) {
-    S.H[set][(size_t)c * S.hcap + slot] = i;
+    gp(S.H[set])[(size_t)c * S.hcap + slot] = i;
   } else {
     const int o = atomicAdd(&S.ovf_n[set], 1);
     if (o < OVF_CAP) {
@@ -160,32 +201,48 @@ __device__ void bin_atom(const SlotDev &S, CtlDev &C, int set, int i, double x, 
   }
 }
 
-// Visit the atoms of cell c of a set in ascending storage index (the order
-// of the row entries themselves depends on atomic timing, so it is not used).
-template <class Visit>
-__device__ __forceinline__ void visit_cell(const SlotDev &S, int set, int c, Visit &&visit) {
-  const int cnt = S.cnt[set][c];
-  const int32_t *__restrict__ row = S.H[set] + (size_t)c * S.hcap;
-  if (cnt <= 4 && S.hcap >= 4) {
-    // load the (at most four) entries together and order them with a
-    // sorting network; unused places hold INT_MAX
-    int a0 = cnt > 0 ? row[0] : INT_MAX, a1 = cnt > 1 ? row[1] : INT_MAX;
-    int a2 = cnt > 2 ? row[2] : INT_MAX, a3 = cnt > 3 ? row[3] : INT_MAX;
-#define MD_CX(p, q) { const int lo = min(p, q), hi = max(p, q); p = lo; q = hi; }
-    MD_CX(a0, a1) MD_CX(a2, a3) MD_CX(a0, a2) MD_CX(a1, a3) MD_CX(a1, a2)
+#define MD_CX(p, q)                             \
+  {                                             \
+    const int lo_ = min(p, q), hi_ = max(p, q); \
+    p = lo_;                                    \
+    q = hi_;                                    \
+  }
+// Compare-exchange network ordering eight values (Batcher odd-even merge).
+__device__ __forceinline__ void sort8(int (&v)[8]) {
+  MD_CX(v[0], v[1]) MD_CX(v[2], v[3]) MD_CX(v[4], v[5]) MD_CX(v[6], v[7])
+  MD_CX(v[0], v[2]) MD_CX(v[1], v[3]) MD_CX(v[4], v[6]) MD_CX(v[5], v[7])
+  MD_CX(v[1], v[2]) MD_CX(v[5], v[6])
+  MD_CX(v[0], v[4]) MD_CX(v[1], v[5]) MD_CX(v[2], v[6]) MD_CX(v[3], v[7])
+  MD_CX(v[2], v[4]) MD_CX(v[3], v[5])
+  MD_CX(v[1], v[2]) MD_CX(v[3], v[4]) MD_CX(v[5], v[6])
+}
 #undef MD_CX
-    if (cnt > 0) visit(a0);
-    if (cnt > 1) visit(a1);
-    if (cnt > 2) visit(a2);
-    if (cnt > 3) visit(a3);
+
+// Visit the atoms of cell c (occupancy cnt) of a set in ascending storage
+// index, passing each one's rank (the order of the row entries themselves
+// depends on atomic timing, so it is not used).  Up to eight atoms held in
+// the row are ordered with a sorting network; larger or overflowing cells
+// take repeated minimum searches over the row and the set's overflow list.
+template <class Visit>
+__device__ __forceinline__ void visit_cell(const SlotDev &S, int set, int c, int cnt,
+                                           Visit &&visit) {
+  const int32_t *__restrict__ row = S.H[set] + (size_t)c * S.hcap;
+  const int inrow = min(cnt, S.hcap);
+  if (cnt <= 8 && inrow == cnt) {
+    int v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = e < cnt ? gp(row)[e] : INT_MAX;
+    sort8(v);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (e < cnt) visit(v[e], e);
     return;
   }
-  const int inrow = min(cnt, S.hcap);
   int last = -1;
   for (int r = 0; r < cnt; ++r) {
     int best = INT_MAX;
     for (int e = 0; e < inrow; ++e) {
-      const int v = row[e];
+      const int v = gp(row)[e];
       best = (v > last && v < best) ? v : best;
     }
     if (cnt > inrow) {
@@ -199,13 +256,10 @@ __device__ __forceinline__ void visit_cell(const SlotDev &S, int set, int c, Vis
     }
     if (best == INT_MAX) break;
     last = best;
-    visit(best);
+    visit(best, r);
   }
 }
 
-// Rebuild decision for step k (Sec. 2.1): rebuilt when the accumulated sum
-// of vmax*dt exceeds delta/2.  disp after step k-1 is recomputed from the
-// committed disp after step k-2 and vmax of step k-1; *disp1 receives it.
 // Maximum of the spread slots of ring entry e (each wave reads all slots).
 __device__ __forceinline__ double ring_max(const SlotDev &S, int64_t e) {
   const int l = threadIdx.x & 63;
@@ -214,6 +268,9 @@ __device__ __forceinline__ double ring_max(const SlotDev &S, int64_t e) {
   return wave_max(v);
 }
 
+// Rebuild decision for step k (Sec. 2.1): rebuilt when the accumulated sum
+// of vmax*dt exceeds delta/2.  disp after step k-1 is recomputed from the
+// committed disp after step k-2 and vmax of step k-1; *disp1 receives it.
 __device__ __forceinline__ bool rebuild_at(const SlotDev &S, const CtlDev &C, int64_t k,
                                            double *disp1) {
   const double D2 = C.disp_ring[mod3(k - 2)];
@@ -231,7 +288,8 @@ __global__ __launch_bounds__(TILE) void k_kick(Tables T) {
   const int nt = T.hdr[HDR_NTILES];
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
     const int r = T.tile_rep[t];
-    const SlotDev &S = slot_of(T, r);
+    if (T.slots[2 * r].n <= 0) continue;
+    const SlotDev &S = slot_held(T, r);
     CtlDev &C = T.ctl[r];
     // errors latched by this launch (err_step = done + 1) do not stop it
     if ((C.err != 0 && C.err_step <= C.done) || !C.clean || C.done >= C.target) continue;
@@ -241,14 +299,14 @@ __global__ __launch_bounds__(TILE) void k_kick(Tables T) {
     const int pb = (int)(k & 1), vb = (int)((k + 1) & 1);
     double f[3];
     for (int a = 0; a < 3; ++a)
-      f[a] = S.fp64 ? ((const double *)S.F)[a * S.npad + i]
-                    : (double)((const float *)S.F)[a * S.npad + i];
+      f[a] = S.fp64 ? gp((const double *)S.F)[a * S.npad + i]
+                    : (double)gp((const float *)S.F)[a * S.npad + i];
     double xn[3];
     for (int a = 0; a < 3; ++a) {
-      const double v = S.V[vb][a][i] + S.hdt * f[a];
-      S.V[vb][a][i] = v;
-      xn[a] = S.P[pb][a][i] + S.dt * v;
-      S.P[pb ^ 1][a][i] = xn[a];
+      const double v = gp(S.V[vb][a])[i] + S.hdt * f[a];
+      gp(S.V[vb][a])[i] = v;
+      xn[a] = gp(S.P[pb][a])[i] + S.dt * v;
+      gp(S.P[pb ^ 1][a])[i] = xn[a];
     }
     bin_atom(S, C, (int)mod3(k + 1), i, xn[0], xn[1], xn[2], k + 1);
   }
@@ -260,9 +318,123 @@ __global__ void k_kick_end(Tables T) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= T.nslots) return;
   CtlDev &C = T.ctl[r];
-  if (slot_of(T, r).n <= 0) return;
+  if (T.slots[2 * r].n <= 0) return;
   if ((C.err != 0 && C.err_step <= C.done) || !C.clean || C.done >= C.target) return;
   C.clean = 0;
+}
+
+// ---------------------------------------------------------------------------
+// (b): the counting sort by cell
+// ---------------------------------------------------------------------------
+// Workgroup t of a replica takes cell tile t (CTILE cells, one per thread):
+// cell_start of the tile's first cell is the sum of the occupancies of the
+// earlier tiles (counted while binning), cell_start of its cells follows
+// from a workgroup scan, and every atom goes to cell_start of its cell plus
+// its rank among the cell's atoms by current storage index -- the sequential
+// layer assignment of Sec. 2.4 read in cell order (Sec. 2.5), i.e. a stable
+// counting sort.  Positions are wrapped on the way (Sec. 2.1, step (b)).
+// Workgroups depend on nobody.
+//   mode == MODE_STEP: step k = base + s + 1 of a run; replicas whose rule
+//   does not fire leave; v(k-1/2) is carried.
+//   otherwise: the held clean state (k = done); v(k) is carried; k_flip
+//   switches the variant afterwards.
+__global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int only) {
+  __shared__ int s_red[4];
+  __shared__ int s_wsum[4];
+  const int nct = T.hdr[HDR_NCTILES];
+  for (int t = xcd_block(blockIdx.x, gridDim.x); t < nct; t += gridDim.x) {
+    const int r = T.ctile_rep[t];
+    if (only >= 0 && r != only) continue;
+    CtlDev &C = T.ctl[r];
+    const SlotDev &S0 = T.slots[2 * r];
+    int64_t k;
+    int var;
+    if (mode == MODE_STEP) {
+      k = C.base + s + 1;
+      if (k > C.target) continue;
+      if (C.err != 0 && C.err_step <= k) continue;
+      var = C.var_ring[mod3(k - 1)];
+      bool rebuild = true;
+      double d1 = 0.0;
+      if (!S0.cell_only) rebuild = rebuild_at(S0, C, k, &d1);
+      if (t == S0.ctile_off && threadIdx.x == 0) {
+        // the one writer of these ring slots for step k
+        C.rb_ring[mod3(k)] = rebuild ? 1 : 0;
+        if (!S0.cell_only) {
+          C.disp_ring[mod3(k - 1)] = d1;
+          if (rebuild && k != C.force_step) C.n_rebuilds += 1;
+        }
+      }
+      if (!rebuild) continue;
+    } else {
+      if (!C.clean) continue;
+      k = C.done;
+      if (C.err != 0 && C.err_step <= k) continue;
+      var = C.var_ring[mod3(k)];
+    }
+    const SlotDev &S = T.slots[2 * r + var];
+    const SlotDev &D = T.slots[2 * r + (var ^ 1)];
+    const int set = (int)mod3(k);
+    const int pb = (int)(k & 1);
+    const int vb = mode == MODE_STEP ? pb : pb ^ 1;
+    const int lt = t - S.ctile_off;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+
+    // atoms in the earlier tiles
+    const auto TC = gp((const int32_t *)S.tcnt[set]);
+    int pre = 0;
+    for (int q = threadIdx.x; q < lt; q += TILE) pre += TC[q];
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    if (l == 0) s_red[w] = pre;
+
+    // workgroup exclusive scan of one cell count per thread
+    const int c = lt * CTILE + threadIdx.x;
+    const int cnt = c < S.ncell ? gp(S.cnt[set])[c] : 0;
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (l >= o) incl += y;
+    }
+    if (l == 63) s_wsum[w] = incl;
+    const int wmax = wave_max_i(cnt);
+    __syncthreads();
+    int before = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+    for (int q = 0; q < w; ++q) before += s_wsum[q];
+    const int base = before + incl - cnt;
+    if (l == 0 && wmax > C.max_h) atomicMax(&C.max_h, wmax);
+    if (c <= S.ncell) gp(S.cs)[c] = base;  // c == ncell: the total, n
+
+    // scatter the cell's atoms in ascending current index
+    if (c < S.ncell && cnt > 0) {
+      const int n = S.n;
+      const double L = S.L, halfL = S.halfL;
+      visit_cell(S, set, c, cnt, [&](int a, int q) {
+        const int p = base + q;
+        if (p >= n || a < 0 || a >= n) return;  // inconsistent counts: never expected
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          gp(D.P[pb][d])[p] = wrap1(gp(S.P[pb][d])[a], L, halfL);
+          gp(D.V[vb][d])[p] = gp(S.V[vb][d])[a];
+        }
+        gp(D.id)[p] = gp(S.id)[a];
+        gp(D.cell)[p] = c;
+      });
+    }
+    __syncthreads();
+  }
+}
+
+// After a sort of the held states (mode != MODE_STEP): switch the replicas
+// that were sorted to their other variant (same gate as k_sort).
+__global__ void k_flip(Tables T, int only) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= T.nslots || (only >= 0 && r != only)) return;
+  if (T.slots[2 * r].n <= 0) return;
+  CtlDev &C = T.ctl[r];
+  if (!C.clean) return;
+  const int64_t k = C.done;
+  if (C.err != 0 && C.err_step <= k) return;
+  C.var_ring[mod3(k)] ^= 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -273,13 +445,17 @@ struct Acc {
   R fx, fy, fz, u, w;
 };
 
+__device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
+__device__ __forceinline__ double recip(double s) { return 1.0 / s; }
+
 // Pair force and energy of Eq. (1) with the soft-sphere shift: for r^2 = s,
 // f = 48 r^-8 (r^-6 - 1/2) (force on i is f d), u = 4 r^-6 (r^-6 - 1) + shift.
+// FP32 uses the hardware reciprocal (1 ulp).
 template <typename R>
 __device__ __forceinline__ void pair_accum(Acc<R> &a, double dx, double dy, double dz, double s,
                                            R ushift) {
   const R sr = (R)s;
-  const R rri = (R)1 / sr;
+  const R rri = recip(sr);
   const R rri3 = rri * rri * rri;
   const R f = (R)48 * rri3 * (rri3 - (R)0.5) * rri;
   a.fx += f * (R)dx;
@@ -294,139 +470,377 @@ __device__ __forceinline__ double img_shift(uint32_t code, double L) {
   return code == 0 ? 0.0 : (code == 1 ? L : -L);
 }
 
-// Compare-exchange network ordering eight values (Batcher odd-even merge).
-#define MD_CX(p, q)                        \
-  {                                        \
-    const int lo_ = min(p, q), hi_ = max(p, q); \
-    p = lo_;                               \
-    q = hi_;                               \
+// Cell coordinate c (one of the 27 offsets, so -1..G) wrapped into [0, G),
+// and the image code of the atoms found there.
+__device__ __forceinline__ int wrap_cell(int c, int G, uint32_t *code) {
+  if (c >= G) {
+    *code = 2;
+    return c - G;
   }
-__device__ __forceinline__ void sort8(int (&v)[8]) {
-  MD_CX(v[0], v[1]) MD_CX(v[2], v[3]) MD_CX(v[4], v[5]) MD_CX(v[6], v[7])
-  MD_CX(v[0], v[2]) MD_CX(v[1], v[3]) MD_CX(v[4], v[6]) MD_CX(v[5], v[7])
-  MD_CX(v[1], v[2]) MD_CX(v[5], v[6])
-  MD_CX(v[0], v[4]) MD_CX(v[1], v[5]) MD_CX(v[2], v[6]) MD_CX(v[3], v[7])
-  MD_CX(v[2], v[4]) MD_CX(v[3], v[5])
-  MD_CX(v[1], v[2]) MD_CX(v[3], v[4]) MD_CX(v[5], v[6])
+  if (c < 0) {
+    *code = 1;
+    return c + G;
+  }
+  *code = 0;
+  return c;
 }
-#undef MD_CX
 
-// Neighbour cell number q (0..26; offsets z-major, x fastest) of the cell
-// (cx, cy, cz), with the periodic image code of its atoms and their shifts.
-struct NCell {
-  int c;
-  uint32_t code;
-  double bx, by, bz;
+// ---------------------------------------------------------------------------
+// LDS window of a tile
+// ---------------------------------------------------------------------------
+// Shared state of a tile's window while the tile is evaluated.
+struct Window {
+  int wt[WSTRIDE];       // staging intervals: count (-1: none), then (start, len, slot)
+  int dl[NROWS * 3];     // per (source row, dz, dy): slot - storage index for the
+                         // target row's main piece, its cell 0 and its cell G-1
+  int rf;                // first source row (cz G + cy) of the tile
+  int whole;             // 1: the window is the whole system, slot = storage index
 };
-__device__ __forceinline__ NCell ncell(int q, int cx, int cy, int cz, int G, double L) {
-  int n[3] = {cx + q % 3 - 1, cy + (q / 3) % 3 - 1, cz + q / 9 - 1};
-  uint32_t im[3];
-  for (int a = 0; a < 3; ++a) {
-    im[a] = 0;
-    if (n[a] >= G) {
-      n[a] -= G;
-      im[a] = 2;
-    } else if (n[a] < 0) {
-      n[a] += G;
-      im[a] = 1;
+
+// At a sort: the candidates of the tile's atoms (sorted, so the tile is a run
+// of cells spanning source rows rf..rl) lie in the 9 target rows (dz, dy) of
+// every source row, in the x-range of that source row widened by one cell
+// (with the periodic wrap).  Wave 0 lists (target row, x-range) for every
+// (source row, dz, dy), sorts the list by target row (bitonic, across the
+// lanes), unites the x-ranges of equal rows, and turns each row into 1-3 cell
+// pieces (cell 0 | main | cell G-1 when the x-range wraps, else one piece),
+// i.e. storage-index intervals via cell_start.  Thread 0 gives the pieces LDS
+// slots in index order up to WCAP (a piece that does not fit stays in global
+// memory) and merges adjacent ones into staging intervals.  The staging table
+// also goes to S.win for the list steps until the next sort.
+__device__ void make_window(const SlotDev &S, int lt, Window &w, int *scratch) {
+  __shared__ int s_np;
+  int *piece = scratch;              // [2 * 192] start, end
+  int *pdelta = scratch + 2 * 192;   // [192] slot - storage index, or NOSLOT
+  const int n = S.n;
+  const int lane = threadIdx.x;
+  int T = INT_MAX, xa = 0, xb = 0, ell = 0, pos = 0, np = 0;
+  bool full = false, w0 = false, wg = false;
+  if (threadIdx.x < 64) {
+    const int G = S.G;
+    const int i_f = lt * TILE, i_l = min(n, i_f + TILE) - 1;
+    const auto CL = gp((const int32_t *)S.cell);
+    const int c_f = CL[i_f], c_l = CL[i_l];
+    const int rf = c_f / G, rl = c_l / G, ns = rl - rf + 1;
+    if (lane == 0) {
+      w.rf = rf;
+      w.whole = n <= WCAP;
+    }
+    if (n <= WCAP || ns * 9 > NROWS) {
+      if (lane == 0) s_np = n <= WCAP ? -2 : -1;  // whole system / no window
+    } else {
+      if (lane < ns * 9) {
+        const int sr = lane / 9, q = lane % 9;
+        const int rho = rf + sr, cz = rho / G, cy = rho % G;
+        uint32_t im;
+        const int tz = wrap_cell(cz + q / 3 - 1, G, &im);
+        const int ty = wrap_cell(cy + q % 3 - 1, G, &im);
+        T = tz * G + ty;
+        xa = (sr == 0 ? c_f % G : 0) - 1;
+        xb = (sr == ns - 1 ? c_l % G : G - 1) + 1;
+        ell = lane;
+      }
+      for (int k = 2; k <= 64; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          const int T2 = __shfl_xor(T, j, 64), a2 = __shfl_xor(xa, j, 64),
+                    b2 = __shfl_xor(xb, j, 64), l2 = __shfl_xor(ell, j, 64);
+          const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+          if (lower == up ? T2 < T : T2 > T) {
+            T = T2;
+            xa = a2;
+            xb = b2;
+            ell = l2;
+          }
+        }
+      const int Tp = __shfl_up(T, 1, 64);
+      const bool lead = T != INT_MAX && (lane == 0 || Tp != T);
+      int ua = xa, ub = xb;
+      for (int d = 1; d < 64; ++d) {
+        const int T2 = __shfl_down(T, d, 64), a2 = __shfl_down(xa, d, 64),
+                  b2 = __shfl_down(xb, d, 64);
+        const bool same = lane + d < 64 && T2 == T && T != INT_MAX;
+        if (same) {
+          ua = min(ua, a2);
+          ub = max(ub, b2);
+        }
+        if (__ballot(same) == 0) break;
+      }
+      int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
+      if (lead) {
+        const int rb = T * G;
+        full = ub - ua + 1 >= G;
+        if (full) {
+          c0[0] = rb;
+          c1[0] = rb + G;
+          np = 1;
+        } else {
+          w0 = ub >= G;  // x = G is cell 0 of the row
+          wg = ua < 0;   // x = -1 is cell G-1 of the row
+          if (w0) {
+            c0[np] = rb;
+            c1[np] = rb + 1;
+            ++np;
+          }
+          c0[np] = rb + max(ua, 0);
+          c1[np] = rb + min(ub, G - 1) + 1;
+          ++np;
+          if (wg) {
+            c0[np] = rb + G - 1;
+            c1[np] = rb + G;
+            ++np;
+          }
+        }
+      }
+      pos = np;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(pos, o, 64);
+        if (lane >= o) pos += y;
+      }
+      const int total = __shfl(pos, 63, 64);
+      pos -= np;
+      const auto CS = gp((const int32_t *)S.cs);
+      for (int e = 0; e < np; ++e) {
+        piece[2 * (pos + e)] = CS[c0[e]];
+        piece[2 * (pos + e) + 1] = CS[c1[e]];
+      }
+      // every lane of a run takes its leader's pieces
+      const unsigned long long lmask = __ballot(lead);
+      const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+      const int ll = 63 - __clzll(lmask & upto);
+      pos = __shfl(pos, ll, 64);
+      np = __shfl(np, ll, 64);
+      full = __shfl((int)full, ll, 64);
+      w0 = __shfl((int)w0, ll, 64);
+      wg = __shfl((int)wg, ll, 64);
+      if (lane == 0) s_np = total;
     }
   }
-  NCell r;
-  r.c = (n[2] * G + n[1]) * G + n[0];
-  r.code = (im[0] | (im[1] << 2) | (im[2] << 4)) << J_BITS;
-  r.bx = img_shift(im[0], L);
-  r.by = img_shift(im[1], L);
-  r.bz = img_shift(im[2], L);
-  return r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int npc = s_np;
+    int nint = 0;
+    if (npc == -2) {
+      w.wt[1] = 0;
+      w.wt[2] = n;
+      w.wt[3] = 0;
+      nint = 1;
+    } else if (npc < 0) {
+      nint = -1;
+    } else {
+      int off = 0;
+      for (int p = 0; p < npc; ++p) {
+        const int s0 = piece[2 * p], len = piece[2 * p + 1] - s0;
+        if (len <= 0) {
+          pdelta[p] = 0;  // empty: no candidate ever reads it
+        } else if (off + len > WCAP) {
+          pdelta[p] = NOSLOT;
+        } else {
+          pdelta[p] = off - s0;
+          if (nint > 0 && w.wt[3 * nint - 2] + w.wt[3 * nint - 1] == s0 &&
+              w.wt[3 * nint] + w.wt[3 * nint - 1] == off) {
+            w.wt[3 * nint - 1] += len;
+          } else if (nint < NWIN) {
+            w.wt[3 * nint + 1] = s0;
+            w.wt[3 * nint + 2] = len;
+            w.wt[3 * nint + 3] = off;
+            ++nint;
+          } else {
+            pdelta[p] = NOSLOT;
+            continue;
+          }
+          off += len;
+        }
+      }
+    }
+    w.wt[0] = nint;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && T != INT_MAX) {
+    const int dm = pdelta[pos + (w0 ? 1 : 0)];
+    w.dl[3 * ell] = dm;
+    w.dl[3 * ell + 1] = full ? dm : (w0 ? pdelta[pos] : NOSLOT);
+    w.dl[3 * ell + 2] = full ? dm : (wg ? pdelta[pos + np - 1] : NOSLOT);
+  }
+  // the staging table for the list steps until the next sort
+  auto WG = gp(S.win) + (size_t)lt * WSTRIDE;
+  const int nint = w.wt[0];
+  if ((int)threadIdx.x < 1 + 3 * max(nint, 0)) WG[threadIdx.x] = w.wt[threadIdx.x];
+  __syncthreads();
 }
 
-// 27-cell traversal (offsets z-major, x fastest; ascending index within a
-// cell) around the wrapped position of atom i.  Accepts r^2 < r_n^2 into W
-// when building, and accumulates the forces of pairs with r^2 < r_c^2.
-// The occupancy and the first four row entries of the next cell are loaded
-// while the current cell is evaluated; a cell's atoms are ordered with a
-// sorting network and their coordinates loaded four at a time.  Cells with
-// more than eight atoms take the general path.
+// Stage the window's atoms (positions of the current step) into LDS.
+__device__ __forceinline__ void stage_window(const int *wt, gcdouble X, gcdouble Y, gcdouble Z,
+                                             double *sx, double *sy, double *sz) {
+  // the intervals fill slots 0 .. total-1 in order: thread t takes slots
+  // t, t + TILE, ... and walks the interval table forward (all loads of a
+  // thread are independent, so they are in flight together)
+  const int nint = wt[0];
+  if (nint <= 0) return;
+  const int total = wt[3 * nint] + wt[3 * nint - 1];
+  int q = 0, end = wt[2];
+  for (int sl = threadIdx.x; sl < total; sl += TILE) {
+    while (sl >= end) {
+      ++q;
+      end = wt[3 * q + 3] + wt[3 * q + 2];
+    }
+    const int j = wt[3 * q + 1] + (sl - wt[3 * q + 3]);
+    sx[sl] = X[j];
+    sy[sl] = Y[j];
+    sz[sl] = Z[j];
+  }
+}
+
+// 27-cell traversal over the sorted atoms (offsets z-major, x fastest;
+// ascending storage index within a cell, which is ascending index before the
+// sort).  The three cells of an x-row are one contiguous range of storage
+// indices unless the row wraps, where it is two.  Candidates are read from
+// the LDS window (slot = storage index + the row piece's offset), or from
+// global memory for a piece the window could not hold.  Accepts r^2 < r_n^2
+// into W when building (window slot, or storage index with GFLAG), and
+// accumulates the forces of pairs with r^2 < r_c^2.  Positions were wrapped
+// by the sort, so they are read as stored.
 template <typename R>
-__device__ __forceinline__ int traverse_cells(const SlotDev &S, int set, int i, int ci,
-                                              const double *__restrict__ X,
-                                              const double *__restrict__ Y,
-                                              const double *__restrict__ Z, double xi, double yi,
-                                              double zi, bool build, bool force, Acc<R> &a) {
+__device__ __forceinline__ int traverse_sorted(const SlotDev &S, int i, int ci, gcdouble X,
+                                               gcdouble Y, gcdouble Z, const Window &w,
+                                               const double *sx, const double *sy,
+                                               const double *sz, double xi, double yi,
+                                               double zi, bool build, bool force, Acc<R> &a) {
   const int G = S.G;
-  const double L = S.L, halfL = S.halfL, rn2 = S.rn2, rc2 = S.rc2;
+  const double L = S.L, rn2 = S.rn2, rc2 = S.rc2;
   const R ushift = (R)S.ushift;
-  const int mcap = S.mcap, hcap = S.hcap;
-  int32_t *__restrict__ Wc = S.W + i;
+  const int mcap = S.mcap;
+  const auto Wc = gp(S.W) + i;
   const size_t np = (size_t)S.npad;
-  const int32_t *__restrict__ CNT = S.cnt[set];
-  const int32_t *__restrict__ HS = S.H[set];
+  const auto CS = gp((const int32_t *)S.cs);
   const int cx = ci % G, cy = (ci / G) % G, cz = ci / (G * G);
-  const bool fast = hcap >= 8;
+  const int sr = ci / G - w.rf;  // source row of the atom within the tile
+  const bool whole = w.whole, rows = !whole && w.wt[0] >= 0;
   int m = 0;
-  auto accept = [&](int j, const NCell &nc, double xj, double yj, double zj) {
-    const double dx = (xi - wrap1(xj, L, halfL)) + nc.bx;
-    const double dy = (yi - wrap1(yj, L, halfL)) + nc.by;
-    const double dz = (zi - wrap1(zj, L, halfL)) + nc.bz;
-    const double s = (dx * dx + dy * dy) + dz * dz;
-    if (s < rn2) {
-      if (build) {
-        if (m < mcap) Wc[(size_t)m * np] = (int32_t)((uint32_t)j | nc.code);
-        ++m;
+  auto range = [&](int lo, int hi, int delta, uint32_t code, double bx, double by, double bz) {
+    const bool lds = delta != NOSLOT;
+    for (int j0 = lo; j0 < hi; j0 += 4) {
+      double xj[4], yj[4], zj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = min(j0 + u, hi - 1);
+        if (lds) {
+          xj[u] = sx[j + delta];
+          yj[u] = sy[j + delta];
+          zj[u] = sz[j + delta];
+        } else {
+          xj[u] = X[j];
+          yj[u] = Y[j];
+          zj[u] = Z[j];
+        }
       }
-      if (force && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + u;
+        if (j >= hi || j == i) continue;
+        const double dx = (xi - xj[u]) + bx;
+        const double dy = (yi - yj[u]) + by;
+        const double dz = (zi - zj[u]) + bz;
+        const double s = (dx * dx + dy * dy) + dz * dz;
+        if (s < rn2) {
+          if (build) {
+            const uint32_t idx = lds ? (uint32_t)(j + delta) : ((uint32_t)j | GFLAG);
+            if (m < mcap) Wc[(size_t)m * np] = (int32_t)(idx | code);
+            ++m;
+          }
+          if (force && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
+        }
+      }
     }
   };
-  // evaluate four ordered candidates (INT_MAX marks an empty place)
-  auto four = [&](const NCell &nc, int v0, int v1, int v2, int v3) {
-    const int vv[4] = {v0, v1, v2, v3};
-    double xj[4], yj[4], zj[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int j = vv[e] != INT_MAX ? vv[e] : i;
-      xj[e] = X[j];
-      yj[e] = Y[j];
-      zj[e] = Z[j];
+  for (int q = 0; q < 9; ++q) {
+    uint32_t iz, iy;
+    const int nz = wrap_cell(cz + q / 3 - 1, G, &iz);
+    const int ny = wrap_cell(cy + q % 3 - 1, G, &iy);
+    const int row = (nz * G + ny) * G;
+    const double by = img_shift(iy, L), bz = img_shift(iz, L);
+    const uint32_t cyz = ((iy << 2) | (iz << 4)) << J_BITS;
+    int dm = NOSLOT, d0 = NOSLOT, dg = NOSLOT;
+    if (whole) {
+      dm = d0 = dg = 0;
+    } else if (rows) {
+      const int e = 3 * (sr * 9 + q);
+      dm = w.dl[e];
+      d0 = w.dl[e + 1];
+      dg = w.dl[e + 2];
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (vv[e] != INT_MAX && vv[e] != i) accept(vv[e], nc, xj[e], yj[e], zj[e]);
-  };
-  NCell cur = ncell(0, cx, cy, cz, G, L);
-  int ccnt = CNT[cur.c];
-  int crow[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) crow[e] = fast ? HS[(size_t)cur.c * hcap + e] : 0;
-  for (int q = 0; q < 27; ++q) {
-    NCell nxt = cur;
-    int ncnt = 0;
-    int nrow[4] = {0, 0, 0, 0};
-    if (q < 26) {
-      nxt = ncell(q + 1, cx, cy, cz, G, L);
-      ncnt = CNT[nxt.c];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) nrow[e] = fast ? HS[(size_t)nxt.c * hcap + e] : 0;
-    }
-    if (fast && ccnt <= 8) {
-      int v[8];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = e < ccnt ? crow[e] : INT_MAX;
-#pragma unroll
-      for (int e = 4; e < 8; ++e) v[e] = e < ccnt ? HS[(size_t)cur.c * hcap + e] : INT_MAX;
-      sort8(v);
-      four(cur, v[0], v[1], v[2], v[3]);
-      if (ccnt > 4) four(cur, v[4], v[5], v[6], v[7]);
+    if (cx > 0 && cx < G - 1) {
+      range(CS[row + cx - 1], CS[row + cx + 2], dm, cyz, 0.0, by, bz);
+    } else if (cx == 0) {
+      range(CS[row + G - 1], CS[row + G], dg, cyz | (1u << J_BITS), L, by, bz);
+      range(CS[row], CS[row + 2], dm, cyz, 0.0, by, bz);
     } else {
-      visit_cell(S, set, cur.c, [&](int j) {
-        if (j != i) accept(j, cur, X[j], Y[j], Z[j]);
-      });
+      range(CS[row + G - 2], CS[row + G], dm, cyz, 0.0, by, bz);
+      range(CS[row], CS[row + 1], d0, cyz | (2u << J_BITS), -L, by, bz);
     }
-    cur = nxt;
-    ccnt = ncnt;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) crow[e] = nrow[e];
   }
   return m;
+}
+
+// 27-cell traversal over the cell-layer rows of set `set` (positions of the
+// current step, unsorted since the last rebuild).  Used for an atom whose
+// neighbour list overflowed its capacity at the last build: forces only.
+template <typename R>
+__device__ void traverse_rows(const SlotDev &S, int set, int i, int ci, gcdouble X, gcdouble Y,
+                              gcdouble Z, double xi, double yi, double zi, Acc<R> &a) {
+  const int G = S.G;
+  const double L = S.L, halfL = S.halfL, rc2 = S.rc2;
+  const R ushift = (R)S.ushift;
+  const int cx = ci % G, cy = (ci / G) % G, cz = ci / (G * G);
+  for (int q = 0; q < 27; ++q) {
+    uint32_t ix, iy, iz;
+    const int nx = wrap_cell(cx + q % 3 - 1, G, &ix);
+    const int ny = wrap_cell(cy + (q / 3) % 3 - 1, G, &iy);
+    const int nz = wrap_cell(cz + q / 9 - 1, G, &iz);
+    const int c = (nz * G + ny) * G + nx;
+    const double bx = img_shift(ix, L), by = img_shift(iy, L), bz = img_shift(iz, L);
+    visit_cell(S, set, c, gp(S.cnt[set])[c], [&](int j, int) {
+      if (j == i) return;
+      const double dx = (xi - wrap1(X[j], L, halfL)) + bx;
+      const double dy = (yi - wrap1(Y[j], L, halfL)) + by;
+      const double dz = (zi - wrap1(Z[j], L, halfL)) + bz;
+      const double s = (dx * dx + dy * dy) + dz * dz;
+      if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
+    });
+  }
+}
+
+// Coordinates of neighbour-list entry e: from the LDS window, or from
+// global memory when the entry carries a storage index.
+__device__ __forceinline__ void entry_pos(uint32_t e, gcdouble X, gcdouble Y, gcdouble Z,
+                                          const double *sx, const double *sy, const double *sz,
+                                          double &xj, double &yj, double &zj) {
+  const uint32_t idx = e & IDX_MASK;
+  if (e & GFLAG) {
+    xj = X[idx];
+    yj = Y[idx];
+    zj = Z[idx];
+  } else {
+    xj = sx[idx];
+    yj = sy[idx];
+    zj = sz[idx];
+  }
+}
+
+// One neighbour-list entry e (index + image code) of atom i.  SHIFT = false
+// when no entry of the wave's current group carries an image code.
+template <typename R, bool SHIFT>
+__device__ __forceinline__ void list_pair(Acc<R> &a, uint32_t e, double xi, double yi, double zi,
+                                          double xj, double yj, double zj, double L, double rc2,
+                                          R ushift) {
+  double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+  if (SHIFT) {
+    const uint32_t code = e >> J_BITS;
+    dx = dx + img_shift(code & 3u, L);
+    dy = dy + img_shift((code >> 2) & 3u, L);
+    dz = dz + img_shift((code >> 4) & 3u, L);
+  }
+  const double s = (dx * dx + dy * dy) + dz * dz;
+  if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
 }
 
 template <typename R>
@@ -437,77 +851,103 @@ __device__ void step_tile(const SlotDev &S, CtlDev &C, int lt, int64_t k, int mo
   const int pb = (int)(k & 1);
   const int vb = mode == MODE_STEP ? pb : pb ^ 1;  // v(k-1/2) during a run, v(k) when clean
   const int set = (int)mod3(k);
-  const double *__restrict__ X = S.P[pb][0];
-  const double *__restrict__ Y = S.P[pb][1];
-  const double *__restrict__ Z = S.P[pb][2];
+  const gcdouble X = gp((const double *)S.P[pb][0]);
+  const gcdouble Y = gp((const double *)S.P[pb][1]);
+  const gcdouble Z = gp((const double *)S.P[pb][2]);
   const bool force = mode != MODE_BUILD;
   const double L = S.L, halfL = S.halfL;
-  Acc<R> a{(R)0, (R)0, (R)0, (R)0, (R)0};
-  int m = 0;
-  double xi = 0, yi = 0, zi = 0;
+
+  // loads that do not wait for the window: own position and velocity, list
+  // length and the first NE list entries (or the own cell when sorted)
+  constexpr int NE = sizeof(R) == 8 ? 8 : 12;
+  const bool list = !cells && force;
+  const auto Wc = gp((const int32_t *)S.W) + i;
+  const size_t np = (size_t)S.npad;
+  double xi = 0, yi = 0, zi = 0, v[3] = {0.0, 0.0, 0.0};
+  int m = 0, ci = 0;
+  uint32_t e[NE];
   if (act) {
     xi = X[i];
     yi = Y[i];
     zi = Z[i];
+    if (force)
+      for (int q = 0; q < 3; ++q) v[q] = gp(S.V[vb][q])[i];
+    if (list) {
+      m = gp(S.m)[i];
+#pragma unroll
+      for (int u = 0; u < NE; ++u) e[u] = u < S.mcap ? (uint32_t)Wc[(size_t)u * np] : 0u;
+    } else if (cells) {
+      ci = gp(S.cell)[i];
+    }
+  }
+
+  // the tile's LDS window: made with the list at a sort, read back otherwise
+  __shared__ double sx[WCAP], sy[WCAP], sz[WCAP];
+  __shared__ Window win;
+  if (cells) {
+    make_window(S, lt, win, (int *)sx);
+  } else if (list) {
+    if (threadIdx.x < WSTRIDE)
+      win.wt[threadIdx.x] = gp((const int32_t *)S.win)[lt * WSTRIDE + threadIdx.x];
+    __syncthreads();
+  }
+  if (cells || list) {
+    stage_window(win.wt, X, Y, Z, sx, sy, sz);
+    __syncthreads();
+  }
+
+  Acc<R> a{(R)0, (R)0, (R)0, (R)0, (R)0};
+  if (act) {
     if (cells) {
-      // (b): the periodic correction is applied to the stored coordinates;
-      // readers of neighbours wrap what they read, so the order of these
-      // in-place writes does not matter.
-      xi = wrap1(xi, L, halfL);
-      yi = wrap1(yi, L, halfL);
-      zi = wrap1(zi, L, halfL);
-      S.P[pb][0][i] = xi;
-      S.P[pb][1][i] = yi;
-      S.P[pb][2][i] = zi;
-      m = traverse_cells<R>(S, set, i, S.cell[i], X, Y, Z, xi, yi, zi, build, force, a);
-      if (build) S.m[i] = m;
-    } else if (force) {
-      m = S.m[i];
+      m = traverse_sorted<R>(S, i, ci, X, Y, Z, win, sx, sy, sz, xi, yi, zi, build, force, a);
+      if (build) gp(S.m)[i] = m;
+    } else if (list) {
       if (m <= S.mcap) {
         const double rc2 = S.rc2;
         const R ushift = (R)S.ushift;
-        const int32_t *__restrict__ Wc = S.W + i;
-        const size_t np = (size_t)S.npad;
-        // four entries at a time: their twelve coordinate loads are in
-        // flight together (same summation order as one at a time)
-        int q = 0;
-        for (; q + 4 <= m; q += 4) {
-          uint32_t e[4];
+        // entries in order, four at a time (their coordinate reads together);
+        // a group without image codes anywhere in the wave skips the shifts
+        auto group = [&](uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
+          const uint32_t eg[4] = {e0, e1, e2, e3};
           double xj[4], yj[4], zj[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) e[u] = (uint32_t)Wc[(size_t)(q + u) * np];
+          for (int u = 0; u < 4; ++u) entry_pos(eg[u], X, Y, Z, sx, sy, sz, xj[u], yj[u], zj[u]);
+          if (__ballot(((e0 | e1 | e2 | e3) >> J_BITS) != 0) == 0) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int j = (int)(e[u] & (uint32_t)J_MASK);
-            xj[u] = X[j];
-            yj[u] = Y[j];
-            zj[u] = Z[j];
+            for (int u = 0; u < 4; ++u)
+              list_pair<R, false>(a, eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2, ushift);
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              list_pair<R, true>(a, eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2, ushift);
+          }
+        };
+        auto single = [&](uint32_t e0) {
+          double xj, yj, zj;
+          entry_pos(e0, X, Y, Z, sx, sy, sz, xj, yj, zj);
+          list_pair<R, true>(a, e0, xi, yi, zi, xj, yj, zj, L, rc2, ushift);
+        };
+        int q = 0;
+#pragma unroll
+        for (int g = 0; g < NE / 4; ++g)
+          if (q + 4 <= m) {
+            group(e[4 * g], e[4 * g + 1], e[4 * g + 2], e[4 * g + 3]);
+            q += 4;
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const uint32_t code = e[u] >> J_BITS;
-            const double dx = (xi - xj[u]) + img_shift(code & 3u, L);
-            const double dy = (yi - yj[u]) + img_shift((code >> 2) & 3u, L);
-            const double dz = (zi - zj[u]) + img_shift((code >> 4) & 3u, L);
-            const double s = (dx * dx + dy * dy) + dz * dz;
-            if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
-          }
-        }
-        for (; q < m; ++q) {
-          const uint32_t e = (uint32_t)Wc[(size_t)q * np];
-          const int j = (int)(e & (uint32_t)J_MASK);
-          const uint32_t code = e >> J_BITS;
-          const double dx = (xi - X[j]) + img_shift(code & 3u, L);
-          const double dy = (yi - Y[j]) + img_shift((code >> 2) & 3u, L);
-          const double dz = (zi - Z[j]) + img_shift((code >> 4) & 3u, L);
-          const double s = (dx * dx + dy * dy) + dz * dz;
-          if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
+        for (int u = 0; u < NE; ++u)
+          if (u >= q && u < m) single(e[u]);
+        if (m > NE) {
+          for (; q + 4 <= m; q += 4)
+            group((uint32_t)Wc[(size_t)q * np], (uint32_t)Wc[(size_t)(q + 1) * np],
+                  (uint32_t)Wc[(size_t)(q + 2) * np], (uint32_t)Wc[(size_t)(q + 3) * np]);
+          for (; q < m; ++q) single((uint32_t)Wc[(size_t)q * np]);
         }
       } else {
         // the list overflowed its capacity at the last build: evaluate this
-        // atom from the cells of the current positions (still exact)
-        traverse_cells<R>(S, set, i, S.cell[i], X, Y, Z, wrap1(xi, L, halfL),
-                          wrap1(yi, L, halfL), wrap1(zi, L, halfL), false, true, a);
+        // atom from the cell-layer rows of the current positions (exact)
+        traverse_rows<R>(S, set, i, gp(S.cell)[i], X, Y, Z, wrap1(xi, L, halfL),
+                         wrap1(yi, L, halfL), wrap1(zi, L, halfL), a);
       }
     }
   }
@@ -515,7 +955,6 @@ __device__ void step_tile(const SlotDev &S, CtlDev &C, int lt, int64_t k, int mo
   // (d), (e) and the next (a)
   double vv = 0.0;
   if (act && force) {
-    double v[3] = {S.V[vb][0][i], S.V[vb][1][i], S.V[vb][2][i]};
     const double f[3] = {(double)a.fx, (double)a.fy, (double)a.fz};
     if (mode == MODE_STEP)
       for (int q = 0; q < 3; ++q) v[q] = v[q] + S.hdt * f[q];  // (d)
@@ -527,18 +966,18 @@ __device__ void step_tile(const SlotDev &S, CtlDev &C, int lt, int64_t k, int mo
         for (int q = 0; q < 3; ++q) {
           v[q] = v[q] + S.hdt * f[q];  // (a) of step k+1
           xn[q] = xo[q] + S.dt * v[q];
-          S.P[pb ^ 1][q][i] = xn[q];
+          gp(S.P[pb ^ 1][q])[i] = xn[q];
         }
         bin_atom(S, C, (int)mod3(k + 1), i, xn[0], xn[1], xn[2], k + 1);
       }
-      for (int q = 0; q < 3; ++q) S.V[pb ^ 1][q][i] = v[q];
+      for (int q = 0; q < 3; ++q) gp(S.V[pb ^ 1][q])[i] = v[q];
     }
     if (mode != MODE_STEP || last) {
-      R *F = (R *)S.F;
+      auto F = gp((R *)S.F);
       F[i] = a.fx;
       F[S.npad + i] = a.fy;
       F[2 * S.npad + i] = a.fz;
-      R *U = (R *)S.UA;
+      auto U = gp((R *)S.UA);
       U[i] = a.u;
       U[S.npad + i] = a.w;
     }
@@ -548,69 +987,82 @@ __device__ void step_tile(const SlotDev &S, CtlDev &C, int lt, int64_t k, int mo
   if (mode == MODE_STEP) {
     const int zs = (int)mod3(k + 2);
     const int c0 = lt * S.cpt, c1 = min(c0 + S.cpt, S.ncell);
-    for (int c = c0 + threadIdx.x; c < c1; c += TILE) S.cnt[zs][c] = 0;
+    for (int c = c0 + threadIdx.x; c < c1; c += TILE) gp(S.cnt[zs])[c] = 0;
+    for (int q = lt * TILE + threadIdx.x; q < S.nctiles; q += S.ntiles * TILE)
+      gp(S.tcnt[zs])[q] = 0;
     if (lt == 0 && threadIdx.x == 0) S.ovf_n[zs] = 0;
   }
 
-  // per-tile partials (fixed reduction order) and the wave maxima of v^2
-  __shared__ double sh[4][8];
+  // the maximum speed of the step (the rebuild rule needs it every step):
+  // v^2 >= 0, so its bit pattern orders like the value
+  __shared__ unsigned long long sv[4];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int mm = act && !S.cell_only ? m : 0;
-  const double ke = wave_sum(vv);
-  const double vmx = wave_max(vv);
-  const double sm = wave_sum((double)mm);
-  const int mmax = wave_max_i(mm);
-  double pe_hi, pe_lo, vr_hi, vr_lo;
-  if (sizeof(R) == 8) {
-    pe_hi = wave_sum((double)a.u);
-    vr_hi = wave_sum((double)a.w);
-    pe_lo = vr_lo = 0.0;
-  } else {
-    F2 pe = wave_sum_f2(F2{(float)a.u, 0.0f});
-    F2 vr = wave_sum_f2(F2{(float)a.w, 0.0f});
-    pe_hi = pe.hi;
-    pe_lo = pe.lo;
-    vr_hi = vr.hi;
-    vr_lo = vr.lo;
-  }
-  if (l == 0) {
-    sh[w][0] = ke;
-    sh[w][1] = vmx;
-    sh[w][2] = pe_hi;
-    sh[w][3] = pe_lo;
-    sh[w][4] = vr_hi;
-    sh[w][5] = vr_lo;
-    sh[w][6] = sm;
-    sh[w][7] = (double)mmax;
+  const unsigned long long vbits = wave_max_u64((unsigned long long)__double_as_longlong(vv));
+  if (l == 0) sv[w] = vbits;
+  // the other properties only where somebody reads them: the last step of a
+  // run, and evaluations of a held state
+  const bool full = mode != MODE_STEP || last;
+  __shared__ double sh[4][8];
+  if (full) {
+    const int mm = act && !S.cell_only ? m : 0;
+    const double ke = wave_sum(vv);
+    const double sm = wave_sum((double)mm);
+    const int mmax = wave_max_i(mm);
+    double pe_hi, pe_lo, vr_hi, vr_lo;
+    if (sizeof(R) == 8) {
+      pe_hi = wave_sum((double)a.u);
+      vr_hi = wave_sum((double)a.w);
+      pe_lo = vr_lo = 0.0;
+    } else {
+      F2 pe = wave_sum_f2(F2{(float)a.u, 0.0f});
+      F2 vr = wave_sum_f2(F2{(float)a.w, 0.0f});
+      pe_hi = pe.hi;
+      pe_lo = pe.lo;
+      vr_hi = vr.hi;
+      vr_lo = vr.lo;
+    }
+    if (l == 0) {
+      sh[w][0] = ke;
+      sh[w][2] = pe_hi;
+      sh[w][3] = pe_lo;
+      sh[w][4] = vr_hi;
+      sh[w][5] = vr_lo;
+      sh[w][6] = sm;
+      sh[w][7] = (double)mmax;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double *q = S.part + (size_t)lt * NPART;
-    if (force) {
-      q[0] = ((sh[0][0] + sh[1][0]) + sh[2][0]) + sh[3][0];
-      q[1] = fmax(fmax(sh[0][1], sh[1][1]), fmax(sh[2][1], sh[3][1]));
-      // one atomic per workgroup, spread over VSPREAD cache lines
-      atomicMax(&S.vring[(mod3(k) * VSPREAD + (lt & (VSPREAD - 1))) * 16],
-                (unsigned long long)__double_as_longlong(q[1]));
-      if (sizeof(R) == 8) {
-        q[2] = ((sh[0][2] + sh[1][2]) + sh[2][2]) + sh[3][2];
-        q[3] = 0.0;
-        q[4] = ((sh[0][4] + sh[1][4]) + sh[2][4]) + sh[3][4];
-        q[5] = 0.0;
-      } else {
-        F2 e{(float)sh[0][2], (float)sh[0][3]}, v{(float)sh[0][4], (float)sh[0][5]};
-        for (int k2 = 1; k2 < 4; ++k2) {
-          e = f2_add(e, F2{(float)sh[k2][2], (float)sh[k2][3]});
-          v = f2_add(v, F2{(float)sh[k2][4], (float)sh[k2][5]});
+    const unsigned long long b01 = sv[0] > sv[1] ? sv[0] : sv[1];
+    const unsigned long long b23 = sv[2] > sv[3] ? sv[2] : sv[3];
+    const unsigned long long vmb = b01 > b23 ? b01 : b23;
+    // one atomic per workgroup, spread over VSPREAD cache lines
+    if (force) atomicMax(&S.vring[(mod3(k) * VSPREAD + (lt & (VSPREAD - 1))) * 16], vmb);
+    if (full) {
+      auto q = gp(S.part) + (size_t)lt * NPART;
+      if (force) {
+        q[0] = ((sh[0][0] + sh[1][0]) + sh[2][0]) + sh[3][0];
+        q[1] = __longlong_as_double((long long)vmb);
+        if (sizeof(R) == 8) {
+          q[2] = ((sh[0][2] + sh[1][2]) + sh[2][2]) + sh[3][2];
+          q[3] = 0.0;
+          q[4] = ((sh[0][4] + sh[1][4]) + sh[2][4]) + sh[3][4];
+          q[5] = 0.0;
+        } else {
+          F2 e{(float)sh[0][2], (float)sh[0][3]}, v2{(float)sh[0][4], (float)sh[0][5]};
+          for (int k2 = 1; k2 < 4; ++k2) {
+            e = f2_add(e, F2{(float)sh[k2][2], (float)sh[k2][3]});
+            v2 = f2_add(v2, F2{(float)sh[k2][4], (float)sh[k2][5]});
+          }
+          q[2] = e.hi;
+          q[3] = e.lo;
+          q[4] = v2.hi;
+          q[5] = v2.lo;
         }
-        q[2] = e.hi;
-        q[3] = e.lo;
-        q[4] = v.hi;
-        q[5] = v.lo;
       }
+      q[6] = ((sh[0][6] + sh[1][6]) + sh[2][6]) + sh[3][6];
+      q[7] = fmax(fmax(sh[0][7], sh[1][7]), fmax(sh[2][7], sh[3][7]));
     }
-    q[6] = ((sh[0][6] + sh[1][6]) + sh[2][6]) + sh[3][6];
-    q[7] = fmax(fmax(sh[0][7], sh[1][7]), fmax(sh[2][7], sh[3][7]));
   }
   __syncthreads();
 }
@@ -622,41 +1074,36 @@ __global__ __launch_bounds__(TILE, 4) void k_step(Tables T, int s, int mode, int
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
     const int r = T.tile_rep[t];
     if (only >= 0 && r != only) continue;
-    const SlotDev &S = slot_of(T, r);
-    if (S.fp64 != (sizeof(R) == 8)) continue;  // the other precision's kernel
+    const SlotDev &S0 = T.slots[2 * r];
+    if (S0.fp64 != (sizeof(R) == 8)) continue;  // the other precision's kernel
     CtlDev &C = T.ctl[r];
     int64_t k;
+    int var;
     bool last = false, cells, build;
-    double disp1 = 0.0;
     if (mode == MODE_STEP) {
       k = C.base + s + 1;
       if (k > C.target) continue;
       last = k == C.target;
-      if (S.cell_only) {
-        cells = true;
-        build = false;
-      } else {
-        build = rebuild_at(S, C, k, &disp1);
-        cells = build;
-      }
+      var = C.var_ring[mod3(k - 1)];
+      // k_sort of this step decided, and if so gathered r(k) into the other variant
+      cells = C.rb_ring[mod3(k)] != 0;
+      build = cells && !S0.cell_only;
+      if (cells) var ^= 1;
     } else {
       if (!C.clean) continue;
       k = C.done;
-      build = !S.cell_only && (force_build || mode == MODE_BUILD);
-      cells = build || S.cell_only;
+      var = C.var_ring[mod3(k)];
+      build = !S0.cell_only && (force_build || mode == MODE_BUILD);
+      cells = build || S0.cell_only;
     }
     // stop at an error of an earlier step; one latched by this launch (while
     // binning r(k+1), err_step = k + 1) must not stop the other workgroups
     if (C.err != 0 && C.err_step <= k) continue;
+    const SlotDev &S = T.slots[2 * r + var];
     const int lt = t - S.tile_off;
     step_tile<R>(S, C, lt, k, mode, cells, build, last);
-    if (mode == MODE_STEP && lt == 0 && threadIdx.x == 0) {
-      // the one writer of these ring slots in this launch
-      if (!S.cell_only) {
-        C.disp_ring[mod3(k - 1)] = disp1;
-        if (build && k != C.force_step) C.n_rebuilds += 1;
-      }
-    }
+    if (mode == MODE_STEP && lt == 0 && threadIdx.x == 0)
+      C.var_ring[mod3(k)] = var;  // the one writer of this ring slot in this launch
     if (mode == MODE_STEP && lt == 0 && threadIdx.x < VSPREAD)
       S.vring[(mod3(k + 1) * VSPREAD + threadIdx.x) * 16] = 0ull;
   }
@@ -668,7 +1115,7 @@ __global__ void k_replay_end(Tables T, int K) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= T.nslots) return;
   CtlDev &C = T.ctl[r];
-  if (slot_of(T, r).n <= 0) return;
+  if (T.slots[2 * r].n <= 0) return;
   if (C.base >= C.target && C.done >= C.target) return;
   int64_t done = C.base + K < C.target ? C.base + K : C.target;
   if (C.err != 0) done = C.err_step - 1 < done ? C.err_step - 1 : done;
@@ -677,14 +1124,6 @@ __global__ void k_replay_end(Tables T, int K) {
   C.base = done;
   // a replica that ran this replay holds a drifted state unless it finished
   C.clean = (done == C.target && C.err == 0) ? 1 : 0;
-}
-
-// Switch every replica (or one) to its other descriptor after k_permute.
-__global__ void k_flip(Tables T, int only) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= T.nslots || (only >= 0 && r != only)) return;
-  if (T.slots[2 * r].n <= 0) return;
-  T.ctl[r].variant ^= 1;
 }
 
 // Host-ordered update of a replica's target (single thread).
@@ -702,9 +1141,9 @@ __global__ void k_set_target(Tables T, int slot, long long target) {
 __global__ __launch_bounds__(TILE) void k_props(Tables T, int only) {
   const int r = blockIdx.x;
   if (r >= T.nslots || (only >= 0 && r != only)) return;
-  const SlotDev &S = slot_of(T, r);
+  if (T.slots[2 * r].n <= 0) return;
+  const SlotDev &S = slot_held(T, r);
   CtlDev &C = T.ctl[r];
-  if (S.n <= 0) return;
   __shared__ double sh[TILE][6];
   double ke = 0, vm = 0, pe = 0, vir = 0, sm = 0, mm = 0;
   for (int t = threadIdx.x; t < S.ntiles; t += TILE) {
@@ -751,14 +1190,15 @@ __global__ __launch_bounds__(TILE) void k_props(Tables T, int only) {
 }
 
 // ---------------------------------------------------------------------------
-// binning of the held state outside a step (creation, reordering)
+// binning of the held state outside a step (creation, host-side sorts)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(TILE) void k_insert(Tables T, int wrap_store, int only) {
   const int nt = T.hdr[HDR_NTILES];
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
     const int r = T.tile_rep[t];
     if (only >= 0 && r != only) continue;
-    const SlotDev &S = slot_of(T, r);
+    if (T.slots[2 * r].n <= 0) continue;
+    const SlotDev &S = slot_held(T, r);
     CtlDev &C = T.ctl[r];
     const int i = (t - S.tile_off) * TILE + threadIdx.x;
     if (i >= S.n) continue;
@@ -774,193 +1214,19 @@ __global__ __launch_bounds__(TILE) void k_insert(Tables T, int wrap_store, int o
   }
 }
 
-// cell_start = exclusive scan of the occupancy of the held state's set, in a
-// single pass: tiles take tickets in launch order and look back at earlier
-// tiles of the same replica.  The status words carry the values themselves,
-// so relaxed device-scope atomics suffice (no fences).
-__device__ __forceinline__ unsigned long long st_pack(uint32_t epoch, int flag, uint32_t v) {
-  return ((unsigned long long)(epoch & 0x3FFFFFFFu) << 34) | ((unsigned long long)flag << 32) | v;
-}
-
-__global__ __launch_bounds__(TILE) void k_scan(Tables T, unsigned epoch, int only) {
-  __shared__ int s_ticket;
-  __shared__ int s_wsum[4];
-  __shared__ int s_excl;
-  const int nct = T.hdr[HDR_NCTILES];
-  for (;;) {
-    if (threadIdx.x == 0) s_ticket = atomicAdd(&T.hdr[HDR_TICKET], 1);
-    __syncthreads();
-    const int t = s_ticket;
-    __syncthreads();
-    if (t >= nct) break;
-    const int r = T.ctile_rep[t];
-    if (only >= 0 && r != only) continue;
-    const SlotDev &S = slot_of(T, r);
-    CtlDev &C = T.ctl[r];
-    const int set = (int)mod3(cur_state(C));
-    const int lt = t - S.ctile_off;
-    const int c0 = lt * CTILE + threadIdx.x * 8;
-    int v[8];
-    int run = 0, vmax = 0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int c = c0 + q;
-      const int cnt = c < S.ncell ? S.cnt[set][c] : 0;
-      v[q] = run;
-      run += cnt;
-      vmax = max(vmax, cnt);
-    }
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    int incl = run;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(incl, o, 64);
-      if (l >= o) incl += y;
-    }
-    if (l == 63) s_wsum[w] = incl;
-    vmax = wave_max_i(vmax);
-    __syncthreads();
-    int before = 0;
-    for (int q = 0; q < w; ++q) before += s_wsum[q];
-    const int excl_thread = before + incl - run;
-    const int agg = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
-    if (l == 0) atomicMax(&C.max_h, vmax);
-    if (threadIdx.x == 0) {
-      unsigned long long *st = S.scan_st;
-      int excl = 0;
-      if (lt == 0) {
-        __hip_atomic_store(&st[0], st_pack(epoch, 2, (uint32_t)agg), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        __hip_atomic_store(&st[lt], st_pack(epoch, 1, (uint32_t)agg), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        int j = lt - 1;
-        long spins = 0;
-        while (j >= 0) {
-          const unsigned long long sv =
-              __hip_atomic_load(&st[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const int flag = (int)((sv >> 32) & 3ull);
-          if ((uint32_t)(sv >> 34) != (epoch & 0x3FFFFFFFu) || flag == 0) {
-            if (++spins > (1l << 24)) {
-              atomicOr(&C.err, ERR_SCAN);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          excl += (int)(sv & 0xFFFFFFFFull);
-          if (flag == 2) break;
-          --j;
-        }
-        __hip_atomic_store(&st[lt], st_pack(epoch, 2, (uint32_t)(excl + agg)), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-      s_excl = excl;
-    }
-    __syncthreads();
-    const int base = s_excl + excl_thread;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int c = c0 + q;
-      if (c < S.ncell) S.cs[c] = base + v[q];
-    }
-    if (c0 <= S.ncell && S.ncell < c0 + 8) S.cs[S.ncell] = base + run;
-    __syncthreads();
-  }
-}
-
-// New position of every atom: cell_start of its cell plus its rank among the
-// cell's atoms by current storage index (the sequential layer assignment of
-// Sec. 2.4 read in cell order, Sec. 2.5).
-__global__ __launch_bounds__(TILE) void k_rank(Tables T, int only) {
-  const int nct = T.hdr[HDR_NCTILES];
-  for (int t = xcd_block(blockIdx.x, gridDim.x); t < nct; t += gridDim.x) {
-    const int r = T.ctile_rep[t];
-    if (only >= 0 && r != only) continue;
-    const SlotDev &S = slot_of(T, r);
-    const CtlDev &C = T.ctl[r];
-    const int set = (int)mod3(cur_state(C));
-    const int lt = t - S.ctile_off;
-    for (int q = 0; q < CTILE / TILE; ++q) {
-      const int c = lt * CTILE + q * TILE + threadIdx.x;
-      if (c >= S.ncell) break;
-      const int start = S.cs[c];
-      const int stop = S.cs[c + 1];
-      int rank = 0;
-      visit_cell(S, set, c, [&](int a) {
-        if (start + rank < stop && start + rank < S.n) {
-          S.perm[start + rank] = a;
-          S.inv[a] = start + rank;
-        }
-        ++rank;
-      });
-    }
-  }
-}
-
-// Gather every per-atom array into cell order; neighbour indices are mapped
-// to the new positions.  Writes the alternate buffers (the host swaps them).
-__global__ __launch_bounds__(TILE) void k_permute(Tables T, int only) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) T.hdr[HDR_TICKET] = 0;  // for the next k_scan
-  const int nt = T.hdr[HDR_NTILES];
-  for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
-    const int r = T.tile_rep[t];
-    if (only >= 0 && r != only) continue;
-    const SlotDev &S = slot_of(T, r);
-    const CtlDev &C = T.ctl[r];
-    const int p = (t - S.tile_off) * TILE + threadIdx.x;
-    if (p >= S.n) continue;
-    const int64_t k = cur_state(C);
-    const int pb = (int)(k & 1), vb = vbuf_of(C);
-    // a replica with a latched error keeps its order (identity gather), so
-    // the descriptor flip below stays consistent without reading its ranks
-    const bool ident = C.err != 0;
-    const int a = ident ? p : S.perm[p];
-    for (int q = 0; q < 3; ++q) {
-      S.P[pb ^ 1][q][p] = S.P[pb][q][a];
-      S.V[vb ^ 1][q][p] = S.V[vb][q][a];
-    }
-    S.id_alt[p] = S.id[a];
-    S.cell_alt[p] = S.cell[a];
-    const int m = S.m[a];
-    S.m_alt[p] = m;
-    const int mq = min(m, S.mcap);
-    const size_t np = (size_t)S.npad;
-    for (int q = 0; q < mq; ++q) {
-      const uint32_t e = (uint32_t)S.W[(size_t)q * np + a];
-      const uint32_t j = e & (uint32_t)J_MASK;
-      S.W_alt[(size_t)q * np + p] =
-          (int32_t)((ident ? j : (uint32_t)S.inv[j]) | (e & ~(uint32_t)J_MASK));
-    }
-    if (S.fp64) {
-      const double *F = (const double *)S.F, *U = (const double *)S.UA;
-      double *Fo = (double *)S.F_alt, *Uo = (double *)S.UA_alt;
-      for (int q = 0; q < 3; ++q) Fo[q * np + p] = F[q * np + a];
-      Uo[p] = U[a];
-      Uo[np + p] = U[np + a];
-    } else {
-      const float *F = (const float *)S.F, *U = (const float *)S.UA;
-      float *Fo = (float *)S.F_alt, *Uo = (float *)S.UA_alt;
-      for (int q = 0; q < 3; ++q) Fo[q * np + p] = F[q * np + a];
-      Uo[p] = U[a];
-      Uo[np + p] = U[np + a];
-    }
-  }
-}
-
 // Clear the cell-layer set of the held state (before re-binning it).
 __global__ __launch_bounds__(TILE) void k_clear_set(Tables T, int only) {
   const int nct = T.hdr[HDR_NCTILES];
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nct; t += gridDim.x) {
     const int r = T.ctile_rep[t];
     if (only >= 0 && r != only) continue;
-    const SlotDev &S = slot_of(T, r);
+    const SlotDev &S = T.slots[2 * r];
     const CtlDev &C = T.ctl[r];
     const int set = (int)mod3(cur_state(C));
     const int lt = t - S.ctile_off;
-    for (int q = 0; q < CTILE / TILE; ++q) {
-      const int c = lt * CTILE + q * TILE + threadIdx.x;
-      if (c < S.ncell) S.cnt[set][c] = 0;
-    }
+    const int c = lt * CTILE + threadIdx.x;
+    if (c < S.ncell) S.cnt[set][c] = 0;
+    if (threadIdx.x == 0) S.tcnt[set][lt] = 0;
     if (lt == 0 && threadIdx.x == 0) S.ovf_n[set] = 0;
   }
 }
@@ -971,6 +1237,10 @@ __global__ __launch_bounds__(TILE) void k_clear_set(Tables T, int only) {
 void launch_kick(const Tables &T, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_kick, dim3(grid), dim3(TILE), 0, s, T);
   hipLaunchKernelGGL(k_kick_end, dim3((T.nslots + TILE - 1) / TILE), dim3(TILE), 0, s, T);
+}
+void launch_sort(const Tables &T, int cgrid, int step_in_replay, int mode, int only,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_sort, dim3(cgrid), dim3(TILE), 0, s, T, step_in_replay, mode, only);
 }
 void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int force_build,
                  int only, int precisions, hipStream_t s) {
@@ -992,12 +1262,6 @@ void launch_props(const Tables &T, int only, hipStream_t s) {
 }
 void launch_insert(const Tables &T, int grid, int wrap_store, int only, hipStream_t s) {
   hipLaunchKernelGGL(k_insert, dim3(grid), dim3(TILE), 0, s, T, wrap_store, only);
-}
-void launch_reorder(const Tables &T, int grid, int cgrid, unsigned epoch, int only,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(cgrid), dim3(TILE), 0, s, T, epoch, only);
-  hipLaunchKernelGGL(k_rank, dim3(cgrid), dim3(TILE), 0, s, T, only);
-  hipLaunchKernelGGL(k_permute, dim3(grid), dim3(TILE), 0, s, T, only);
 }
 void launch_flip(const Tables &T, int only, hipStream_t s) {
   hipLaunchKernelGGL(k_flip, dim3((T.nslots + TILE - 1) / TILE), dim3(TILE), 0, s, T, only);

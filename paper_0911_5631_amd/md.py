@@ -53,8 +53,11 @@ class TorchAllocator:
                 return None
 
         def _free(ptr, _ctx):
-            if ptr:
-                self._torch.cuda.caching_allocator_delete(ptr)
+            # during interpreter shutdown torch may already be torn down; the
+            # process then returns the memory anyway
+            cuda = getattr(self._torch, "cuda", None)
+            if ptr and cuda is not None and getattr(cuda, "caching_allocator_delete", None):
+                cuda.caching_allocator_delete(ptr)
 
         self._alloc_cb = L.ALLOC_FN(_alloc)
         self._free_cb = L.FREE_FN(_free)
