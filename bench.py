@@ -115,13 +115,16 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.calibrate_copy > 0:
+        # a plain device-to-device copy of known size whose source is no
+        # longer in the last-level cache (a 1 GiB buffer is written after it)
         nel = args.calibrate_copy * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        flush = torch.full((1 << 28,), 2.0, dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, flush
     wl = {"sp_256k": I.sp_256k, "sp_4m": I.sp_4m, "sp_small": I.sp_small_cells}[args.workload]()
     n = wl.n
     s = System(wl.pos, wl.vel, wl.box, shell=wl.shell, dt=wl.dt, precision=wl.precision)
