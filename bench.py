@@ -72,6 +72,65 @@ def traffic_per_launch():
     return t.get("hbm_bytes_per_launch")
 
 
+def batched(n_replicas: int, steps: int, n_solo: int, solo_steps: int) -> dict:
+    """Replicas of uneven size (N = 4 k^3, k ~ U{6..20}, rho ~ U[0.7, 0.9],
+    T ~ U[0.8, 1.5]) advanced together in one batch (launch configuration
+    autotuned on the run itself) against the same systems run one after
+    another through the single-system path."""
+    import torch
+    from paper_0911_5631_amd import inputs as I
+    from paper_0911_5631_amd.md import Batch, System
+    from paper_0911_5631_amd.tune import autotune
+    systems = I.replica_batch(n_replicas=n_replicas, steps=steps)
+    work = float(sum(s.n * s.steps for s in systems))
+    b = Batch(64 << 30, n_replicas, 64)
+    for s in systems:
+        b.admit(s.pos, s.vel, s.box, s.steps, shell=s.shell, dt=s.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tune = autotune(b, runs=1)
+    done = 0
+    while done < n_replicas:
+        b.run()
+        for slot in b.poll():
+            b.release(slot)
+            done += 1
+    el = time.perf_counter() - t0
+    b.close()
+    # one after another, each system alone (a sample of the same replicas)
+    solo_work = 0.0
+    t1 = time.perf_counter()
+    for s in systems[:n_solo]:
+        sy = System(s.pos, s.vel, s.box, shell=s.shell, dt=s.dt)
+        sy.step(solo_steps)
+        sy.props()
+        sy.close()
+        solo_work += s.n * solo_steps
+    el_solo = time.perf_counter() - t1
+    return {"replicas": n_replicas, "atoms": int(sum(s.n for s in systems)), "steps": steps,
+            "atom_steps_per_s": work / el, "seconds": el,
+            "sequential_atom_steps_per_s": solo_work / el_solo,
+            "sequential_sample": f"first {n_solo} replicas x {solo_steps} steps, each created, "
+                                 "stepped and read back alone",
+            "speedup_vs_sequential": (work / el) / (solo_work / el_solo),
+            "autotuned": tune["best"]}
+
+
+def served(n_requests: int, rate: float, k_hi: int, steps_lo: int, steps_hi: int,
+           budget_gb: float) -> dict:
+    """A Poisson trace of requests served through one continuously refilled
+    batch under an HBM budget: latency percentiles and aggregate rate."""
+    from paper_0911_5631_amd import inputs as I
+    from paper_0911_5631_amd.server import serve
+    reqs = I.served_stream(n_requests=n_requests, rate=rate, k_hi=k_hi, steps_lo=steps_lo,
+                           steps_hi=steps_hi)
+    res = serve(reqs, int(budget_gb * (1 << 30)), max_slots=min(256, n_requests))
+    out = {k: v for k, v in res.items() if k != "served"}
+    out.update({"rate_per_s": rate, "k_range": [6, k_hi], "steps_range": [steps_lo, steps_hi],
+                "hbm_budget_gb": budget_gb})
+    return out
+
+
 def cpu_baseline(sys_in, budget_s: float):
     """The FP64 oracle on this host: same system, steps from the start until
     the time budget is used (at least 50 steps)."""
@@ -99,7 +158,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample (0: skip)")
-    ap.add_argument("--workload", default="sp_256k", choices=["sp_256k", "sp_4m", "sp_small"])
+    ap.add_argument("--workload", default="sp_256k",
+                    choices=["sp_256k", "sp_4m", "sp_small", "batch", "served"],
+                    help="single system (default sp_256k); 'batch' / 'served' run only the full "
+                         "batched-replica or served-stream workload and print its JSON line")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the reduced batched and served sections of the default run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (a counter calibration "
                          "point for profilers), untimed")
@@ -114,6 +178,20 @@ def main() -> int:
     from paper_0911_5631_amd.md import System
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        r = batched(256, 5000, 32, 1000)
+        print(json.dumps({"metric": "atom-steps/s, 256 batched replicas", "value": r["atom_steps_per_s"],
+                          "unit": "atom-steps/s", "n_gpus": 1, "higher_is_better": True,
+                          "data": "synthetic", "config": {"workload": "replica_batch_256"},
+                          "batched": r}), flush=True)
+        return 0
+    if args.workload == "served":
+        r = served(256, 50.0, 50, 1000, 20000, 32.0)
+        print(json.dumps({"metric": "served request latency p50/p99 and atom-steps/s",
+                          "value": r["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1,
+                          "higher_is_better": True, "data": "synthetic",
+                          "config": {"workload": "served_stream_256"}, "served": r}), flush=True)
+        return 0
     if args.calibrate_copy > 0:
         # a plain device-to-device copy of known size whose source is no
         # longer in the last-level cache (a 1 GiB buffer is written after it)
@@ -192,6 +270,17 @@ def main() -> int:
                   "n_rebuilds": pr["n_rebuilds"], "step": pr["step"]},
     }
     s.close()
+    if not args.no_extras:
+        # the batched-replica and served-stream workloads, reduced in steps
+        # and requests so the default run stays within minutes (the full ones:
+        # --workload batch / --workload served)
+        out["batched"] = batched(256, 400, 32, 200)
+        print(f"# batched: {out['batched']['atom_steps_per_s']:.4g} atom-steps/s "
+              f"({out['batched']['speedup_vs_sequential']:.1f}x sequential)", file=sys.stderr,
+              flush=True)
+        out["served"] = served(64, 200.0, 20, 200, 2000, 32.0)
+        print(f"# served: p50 {out['served']['p50_latency_s']:.3f} s, p99 "
+              f"{out['served']['p99_latency_s']:.3f} s", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -230,6 +230,12 @@ void md_destroy(md_system *s);
 md_status md_batch_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_run,
                           const md_allocator *a, void *hip_stream, md_batch **out);
 
+/* Launch configuration of later runs: steps replayed per md_batch_run
+ * (1..64) and workgroups per kernel launch (0: 2048; tiles beyond the grid
+ * are taken in further passes).  Neither changes any arithmetic or its
+ * order, so trajectories stay bit-identical; used by the autotuner.  Sync. */
+md_status md_batch_configure(md_batch *b, int32_t steps_per_run, int32_t grid);
+
 /* Admit a system that is to advance n_steps steps; evaluates its step 0
  * (as md_create).  MD_ERR_OOM if it does not fit the remaining budget,
  * MD_ERR_NO_SLOT if every slot is busy; the caller retries later.  Sync. */

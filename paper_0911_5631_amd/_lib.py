@@ -28,7 +28,7 @@ EXPORTS = (
     "md_build_nebr", "md_forces", "md_step", "md_props", "md_get_state",
     "md_get_atom_energies", "md_set_state", "md_get_cells", "md_get_bins", "md_get_pairs",
     "md_profile", "md_kernel_time", "md_destroy", "md_batch_create", "md_batch_admit",
-    "md_batch_run", "md_batch_poll", "md_batch_props", "md_batch_get_state",
+    "md_batch_configure", "md_batch_run", "md_batch_poll", "md_batch_props", "md_batch_get_state",
     "md_batch_release", "md_batch_usage", "md_batch_destroy",
 )
 
@@ -124,6 +124,8 @@ def lib():
                                       _P, C.POINTER(_P)]
         L.md_batch_admit.restype = st
         L.md_batch_admit.argtypes = [_P, C.POINTER(md_params), _D, _D, C.c_int64, _I32]
+        L.md_batch_configure.restype = st
+        L.md_batch_configure.argtypes = [_P, C.c_int32, C.c_int32]
         L.md_batch_run.restype = st
         L.md_batch_run.argtypes = [_P]
         L.md_batch_poll.restype = st

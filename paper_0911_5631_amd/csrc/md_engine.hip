@@ -8,7 +8,8 @@
 // to 64): per step a launch of the sort kernel (which does work only where
 // the rebuild rule fires) and one of the step kernel, then one counter
 // update.  All kernel arguments are pointers to device tables, so graphs stay
-// valid when slots are admitted or released.
+// valid when slots are admitted or released -- except when the tile tables
+// have to grow: then the graphs are dropped and captured again.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -372,6 +373,10 @@ md_status upload_tables(Engine *e) {
     nct += r->g.nctiles;
   }
   if (nt > e->tile_cap || nct > e->ctile_cap) {
+    // the captured graphs hold the table pointers in their kernel arguments:
+    // drop them before the tables move (the stream is idle here)
+    for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    e->graphs.clear();
     e->dfree(e->d_tile_rep);
     e->dfree(e->d_ctile_rep);
     e->tile_cap = std::max(nt, 2 * e->tile_cap);
@@ -1168,6 +1173,25 @@ md_status md_batch_create(size_t hbm_budget, int32_t max_slots, int32_t steps_pe
     return MD_ERR_OOM;
   }
   *out = b;
+  return MD_OK;
+}
+
+md_status md_batch_configure(md_batch *b, int32_t steps_per_run, int32_t grid) {
+  if (!b || !b->e || steps_per_run <= 0 || steps_per_run > GRAPH_CHUNK || grid < 0 ||
+      grid > 65535)
+    return MD_ERR_INVALID_ARG;
+  Engine *e = b->e;
+  if (e->sticky_hip) return MD_ERR_HIP;
+  hipError_t err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("configure", err);
+  const int g = grid > 0 ? grid : MAX_GRID;
+  if (g != e->grid) {
+    // captured graphs bake the grid in
+    for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    e->graphs.clear();
+  }
+  e->grid = e->cgrid = g;
+  e->steps_per_run = steps_per_run;
   return MD_OK;
 }
 

@@ -175,8 +175,25 @@ def replica_batch(n_replicas: int = 256, k_lo: int = 6, k_hi: int = 20, steps: i
 
 @dataclasses.dataclass
 class Request:
+    """One served request: its arrival time and the parameters of its system.
+    The positions and velocities are generated only when asked for (a trace of
+    requests up to 5e5 atoms each stays small until admission)."""
     arrival: float        # seconds after the stream starts
-    system: System
+    name: str
+    n_cells: int          # fcc unit cells per edge: N = 4 n_cells^3
+    rho: float
+    temperature: float
+    steps: int
+    seed: int
+    shell: float = 0.4
+
+    @property
+    def n(self) -> int:
+        return 4 * self.n_cells ** 3
+
+    def system(self) -> System:
+        return fcc_system(self.name, self.n_cells, self.rho, self.temperature,
+                          shell=self.shell, steps=self.steps, precision="fp32", seed=self.seed)
 
 
 def served_stream(n_requests: int = 256, rate: float = 50.0, k_lo: int = 6, k_hi: int = 50,
@@ -194,7 +211,5 @@ def served_stream(n_requests: int = 256, rate: float = 50.0, k_lo: int = 6, k_hi
         rho = float(rng.uniform(0.7, 0.9))
         T = float(rng.uniform(0.8, 1.5))
         steps = int(rng.integers(steps_lo, steps_hi + 1))
-        sysr = fcc_system(f"request{r}", k, rho, T, shell=shell, steps=steps,
-                          precision="fp32", seed=_replica_seed(seed, r))
-        out.append(Request(t, sysr))
+        out.append(Request(t, f"request{r}", k, rho, T, steps, _replica_seed(seed, r), shell))
     return out

@@ -219,6 +219,7 @@ class Batch:
                                     C.byref(h)), "md_batch_create")
         self._h = h
         self.max_slots = max_slots
+        self.steps_per_run = int(steps_per_run)
         self.n_of = {}
 
     def admit(self, pos, vel, box: float, n_steps: int, **params) -> int:
@@ -241,6 +242,12 @@ class Batch:
             if e.code in (-3, -9):
                 return None
             raise
+
+    def configure(self, steps_per_run: int, grid: int = 0) -> None:
+        """Launch configuration of later runs (changes no arithmetic)."""
+        check(lib().md_batch_configure(self._h, int(steps_per_run), int(grid)),
+              "md_batch_configure")
+        self.steps_per_run = int(steps_per_run)
 
     def run(self) -> None:
         check(lib().md_batch_run(self._h), "md_batch_run")

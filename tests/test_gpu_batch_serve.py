@@ -1,0 +1,114 @@
+"""Batched replicas under the autotuner, and the serving loop.
+
+Bar: every system's final state is the same bit for bit as the same system
+run alone through md_system (the launch configuration and the mix change no
+arithmetic); admission never exceeds the HBM budget; every request is served
+once, with latency >= queueing delay >= 0.
+"""
+import numpy as np
+import pytest
+
+from paper_0911_5631_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+def _solo(pos, vel, L, steps):
+    from paper_0911_5631_amd.md import System
+    s = System(pos, vel, L, shell=0.4)
+    s.step(steps)
+    p, v, _, step = s.get_state()
+    pr = s.props()
+    s.close()
+    return p, v, step, pr
+
+
+def test_autotuned_batch_equals_solo():
+    from paper_0911_5631_amd.md import Batch
+    from paper_0911_5631_amd.tune import autotune
+    systems = I.replica_batch(n_replicas=6, k_lo=4, k_hi=9, steps=700, seed=21)
+    b = Batch(1 << 31, 8, 64)
+    slot_of = {}
+    for k, s in enumerate(systems):
+        slot_of[b.admit(s.pos, s.vel, s.box, s.steps, shell=s.shell)] = k
+    res = autotune(b, candidates=((8, 64), (16, 512), (32, 2048), (64, 96)), runs=1)
+    assert res["best"] in res["trials"] and len(res["trials"]) == 4
+    out = {}
+    for _ in range(100):
+        if len(out) == len(systems):
+            break
+        b.run()
+        for slot in b.poll():
+            if slot_of[slot] not in out:
+                out[slot_of[slot]] = b.get_state(slot)
+                b.release(slot)
+    b.close()
+    assert len(out) == len(systems)
+    for k, s in enumerate(systems):
+        p, v, step, _ = _solo(s.pos, s.vel, s.box, s.steps)
+        gp, gv, gstep = out[k]
+        assert gstep == step == s.steps
+        assert np.array_equal(gp, p) and np.array_equal(gv, v), k
+
+
+def test_serving_loop_small_trace():
+    from paper_0911_5631_amd.md import make_params, md_query_bytes
+    from paper_0911_5631_amd.server import serve
+    reqs = I.served_stream(n_requests=10, rate=200.0, k_lo=4, k_hi=8, steps_lo=40,
+                           steps_hi=300, seed=33)
+    # a budget that holds about three of these systems at once: admission queues
+    need = [md_query_bytes(make_params(r.n, r.system().box, shell=r.shell)) for r in reqs]
+    budget = int(3.2 * max(need))
+    res = serve(reqs, budget, max_slots=8, steps_per_run=32, keep_state=True)
+    assert res["n_requests"] == len(reqs)
+    assert res["peak_bytes"] <= budget
+    assert sorted(r.name for r in res["served"]) == sorted(r.name for r in reqs)
+    for rec in res["served"]:
+        assert rec.latency >= rec.queueing >= -1e-9
+        assert rec.props["step"] == rec.steps
+    assert 0 < res["p50_latency_s"] <= res["p99_latency_s"]
+    assert res["atom_steps"] == sum(r.n * r.steps for r in reqs)
+    # served results are the systems' own trajectories, bit for bit
+    by_name = {r.name: r for r in reqs}
+    for rec in res["served"][:4]:
+        s = by_name[rec.name].system()
+        p, v, step, _ = _solo(s.pos, s.vel, s.box, rec.steps)
+        assert step == rec.steps
+        assert np.array_equal(rec.pos, p) and np.array_equal(rec.vel, v), rec.name
+
+
+def test_tables_grow_after_graph_capture():
+    # a one-tile system runs first (its replay graph is captured), then an
+    # admission needs more tiles than the tile tables hold, so they move and
+    # the graphs must be captured again; both systems must still match solo
+    from paper_0911_5631_amd.md import Batch
+    small = I.replica_batch(n_replicas=1, k_lo=4, k_hi=4, steps=300, seed=51)[0]
+    big = I.replica_batch(n_replicas=1, k_lo=12, k_hi=12, steps=100, seed=52)[0]
+    b = Batch(1 << 31, 4, 16)
+    slot_of = {b.admit(small.pos, small.vel, small.box, small.steps, shell=0.4): 0}
+    b.run()
+    assert b.poll() == []
+    slot_of[b.admit(big.pos, big.vel, big.box, big.steps, shell=0.4)] = 1
+    out = {}
+    for _ in range(100):
+        if len(out) == 2:
+            break
+        b.run()
+        for slot in b.poll():
+            out[slot_of[slot]] = b.get_state(slot)
+            b.release(slot)
+    b.close()
+    for k, s in enumerate((small, big)):
+        p, v, step, _ = _solo(s.pos, s.vel, s.box, s.steps)
+        gp, gv, gstep = out[k]
+        assert gstep == step == s.steps
+        assert np.array_equal(gp, p) and np.array_equal(gv, v), k
