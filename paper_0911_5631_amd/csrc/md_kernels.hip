@@ -28,6 +28,8 @@
 
 #include <limits.h>
 
+#include <type_traits>
+
 #include "md_device.h"
 #include "md_kernels.h"
 
@@ -716,14 +718,19 @@ __device__ __forceinline__ int traverse_sorted(const SlotDev &S, int i, int ci, 
   const int sr = ci / G - w.rf;  // source row of the atom within the tile
   const bool whole = w.whole, rows = !whole && w.wt[0] >= 0;
   int m = 0;
-  auto range = [&](int lo, int hi, int delta, uint32_t code, double bx, double by, double bz) {
-    const bool lds = delta != NOSLOT;
+  // candidates j of [lo, hi); FROM_LDS: every lane of the wave reads the
+  // window (the usual case: one code path, the reads of four candidates in
+  // flight together), else each lane reads where its piece lives
+  auto candidates = [&](auto from_lds, int lo, int hi, int delta, uint32_t code, double bx,
+                        double by, double bz) {
+    constexpr bool ALL_LDS = decltype(from_lds)::value;
+    const bool lds = ALL_LDS || delta != NOSLOT;
     for (int j0 = lo; j0 < hi; j0 += 4) {
       double xj[4], yj[4], zj[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = min(j0 + u, hi - 1);
-        if (lds) {
+        if (ALL_LDS || lds) {
           xj[u] = sx[j + delta];
           yj[u] = sy[j + delta];
           zj[u] = sz[j + delta];
@@ -751,6 +758,12 @@ __device__ __forceinline__ int traverse_sorted(const SlotDev &S, int i, int ci, 
         }
       }
     }
+  };
+  auto range = [&](int lo, int hi, int delta, uint32_t code, double bx, double by, double bz) {
+    if (__ballot(delta == NOSLOT && lo < hi) == 0)
+      candidates(std::true_type{}, lo, hi, delta, code, bx, by, bz);
+    else
+      candidates(std::false_type{}, lo, hi, delta, code, bx, by, bz);
   };
   for (int q = 0; q < 9; ++q) {
     uint32_t iz, iy;
@@ -910,8 +923,20 @@ __device__ void step_tile(const SlotDev &S, CtlDev &C, int lt, int64_t k, int mo
         auto group = [&](uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
           const uint32_t eg[4] = {e0, e1, e2, e3};
           double xj[4], yj[4], zj[4];
+          if (__ballot(((e0 | e1 | e2 | e3) & GFLAG) != 0) == 0) {
+            // the usual case: every entry of the wave is a window slot
 #pragma unroll
-          for (int u = 0; u < 4; ++u) entry_pos(eg[u], X, Y, Z, sx, sy, sz, xj[u], yj[u], zj[u]);
+            for (int u = 0; u < 4; ++u) {
+              const uint32_t sl = eg[u] & IDX_MASK;
+              xj[u] = sx[sl];
+              yj[u] = sy[sl];
+              zj[u] = sz[sl];
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              entry_pos(eg[u], X, Y, Z, sx, sy, sz, xj[u], yj[u], zj[u]);
+          }
           if (__ballot(((e0 | e1 | e2 | e3) >> J_BITS) != 0) == 0) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
