@@ -48,6 +48,14 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gp(T *p) {
 }
 typedef const __attribute__((address_space(1))) double *gcdouble;
 
+// Replica descriptors are written by the host only, between launches: read
+// through the constant address space their fields are scalar loads held in
+// SGPRs (a wave-uniform descriptor) instead of vector loads into VGPRs.
+typedef const __attribute__((address_space(4))) SlotDev SlotC;
+__device__ __forceinline__ SlotC &slot(const Tables &T, int idx) {
+  return *(SlotC *)(T.slots + idx);
+}
+
 // Workgroups go to the 8 XCDs round-robin; renumber them so that each XCD
 // walks a contiguous range of tiles and neighbouring atoms share an L2.
 __device__ __forceinline__ int xcd_block(int b, int g) {
@@ -125,7 +133,7 @@ __device__ __forceinline__ int cell_coord(double x, double halfL, double invW, i
   return (int)fmin(fmax(q, 0.0), (double)(G - 1));
 }
 
-__device__ __forceinline__ int cell_of(const SlotDev &S, double x, double y, double z) {
+__device__ __forceinline__ int cell_of(SlotC &S, double x, double y, double z) {
   const int G = S.G;
   return (cell_coord(z, S.halfL, S.invW, G) * G + cell_coord(y, S.halfL, S.invW, G)) * G +
          cell_coord(x, S.halfL, S.invW, G);
@@ -133,9 +141,9 @@ __device__ __forceinline__ int cell_of(const SlotDev &S, double x, double y, dou
 
 // Descriptor of the state a replica holds between launches (r(done), or the
 // drifted r(done+1), which lives in the same variant).
-__device__ __forceinline__ const SlotDev &slot_held(const Tables &T, int r) {
+__device__ __forceinline__ SlotC &slot_held(const Tables &T, int r) {
   const CtlDev &C = T.ctl[r];
-  return T.slots[2 * r + C.var_ring[mod3(C.done)]];
+  return slot(T, 2 * r + C.var_ring[mod3(C.done)]);
 }
 
 // State index held by a replica between launches.
@@ -151,7 +159,7 @@ __device__ __forceinline__ void latch_error(CtlDev &C, int bits, int64_t step) {
 // Cell and layer assignment of one atom (Secs. 2.2, 2.4): the atom's cell
 // from its wrapped coordinates, a layer slot from the cell's occupancy
 // counter (atomic), the row entry, or the set's overflow list beyond hcap.
-__device__ void bin_atom(const SlotDev &S, CtlDev &C, int set, int i, double x, double y,
+__device__ void bin_atom(SlotC &S, CtlDev &C, int set, int i, double x, double y,
                          double z, int64_t step) {
   // Called by a prefix of the lanes of a wave (the active atoms of a tile).
   int bad = 0;
@@ -226,7 +234,7 @@ __device__ __forceinline__ void sort8(int (&v)[8]) {
 // the row are ordered with a sorting network; larger or overflowing cells
 // take repeated minimum searches over the row and the set's overflow list.
 template <class Visit>
-__device__ __forceinline__ void visit_cell(const SlotDev &S, int set, int c, int cnt,
+__device__ __forceinline__ void visit_cell(SlotC &S, int set, int c, int cnt,
                                            Visit &&visit) {
   const int32_t *__restrict__ row = S.H[set] + (size_t)c * S.hcap;
   const int inrow = min(cnt, S.hcap);
@@ -263,7 +271,7 @@ __device__ __forceinline__ void visit_cell(const SlotDev &S, int set, int c, int
 }
 
 // Maximum of the spread slots of ring entry e (each wave reads all slots).
-__device__ __forceinline__ double ring_max(const SlotDev &S, int64_t e) {
+__device__ __forceinline__ double ring_max(SlotC &S, int64_t e) {
   const int l = threadIdx.x & 63;
   double v = 0.0;
   if (l < VSPREAD) v = __longlong_as_double((long long)S.vring[(e * VSPREAD + l) * 16]);
@@ -273,7 +281,7 @@ __device__ __forceinline__ double ring_max(const SlotDev &S, int64_t e) {
 // Rebuild decision for step k (Sec. 2.1): rebuilt when the accumulated sum
 // of vmax*dt exceeds delta/2.  disp after step k-1 is recomputed from the
 // committed disp after step k-2 and vmax of step k-1; *disp1 receives it.
-__device__ __forceinline__ bool rebuild_at(const SlotDev &S, const CtlDev &C, int64_t k,
+__device__ __forceinline__ bool rebuild_at(SlotC &S, const CtlDev &C, int64_t k,
                                            double *disp1) {
   const double D2 = C.disp_ring[mod3(k - 2)];
   const double V1 = ring_max(S, mod3(k - 1));
@@ -290,8 +298,8 @@ __global__ __launch_bounds__(TILE) void k_kick(Tables T) {
   const int nt = T.hdr[HDR_NTILES];
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
     const int r = T.tile_rep[t];
-    if (T.slots[2 * r].n <= 0) continue;
-    const SlotDev &S = slot_held(T, r);
+    if (slot(T, 2 * r).n <= 0) continue;
+    SlotC &S = slot_held(T, r);
     CtlDev &C = T.ctl[r];
     // errors latched by this launch (err_step = done + 1) do not stop it
     if ((C.err != 0 && C.err_step <= C.done) || !C.clean || C.done >= C.target) continue;
@@ -320,7 +328,7 @@ __global__ void k_kick_end(Tables T) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= T.nslots) return;
   CtlDev &C = T.ctl[r];
-  if (T.slots[2 * r].n <= 0) return;
+  if (slot(T, 2 * r).n <= 0) return;
   if ((C.err != 0 && C.err_step <= C.done) || !C.clean || C.done >= C.target) return;
   C.clean = 0;
 }
@@ -348,7 +356,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     const int r = T.ctile_rep[t];
     if (only >= 0 && r != only) continue;
     CtlDev &C = T.ctl[r];
-    const SlotDev &S0 = T.slots[2 * r];
+    SlotC &S0 = slot(T, 2 * r);
     int64_t k;
     int var;
     if (mode == MODE_STEP) {
@@ -374,8 +382,8 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
       if (C.err != 0 && C.err_step <= k) continue;
       var = C.var_ring[mod3(k)];
     }
-    const SlotDev &S = T.slots[2 * r + var];
-    const SlotDev &D = T.slots[2 * r + (var ^ 1)];
+    SlotC &S = slot(T, 2 * r + var);
+    SlotC &D = slot(T, 2 * r + (var ^ 1));
     const int set = (int)mod3(k);
     const int pb = (int)(k & 1);
     const int vb = mode == MODE_STEP ? pb : pb ^ 1;
@@ -431,7 +439,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
 __global__ void k_flip(Tables T, int only) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= T.nslots || (only >= 0 && r != only)) return;
-  if (T.slots[2 * r].n <= 0) return;
+  if (slot(T, 2 * r).n <= 0) return;
   CtlDev &C = T.ctl[r];
   if (!C.clean) return;
   const int64_t k = C.done;
@@ -510,7 +518,7 @@ struct Window {
 // slots in index order up to WCAP (a piece that does not fit stays in global
 // memory) and merges adjacent ones into staging intervals.  The staging table
 // also goes to S.win for the list steps until the next sort.
-__device__ void make_window(const SlotDev &S, int lt, Window &w, int *scratch) {
+__device__ void make_window(SlotC &S, int lt, Window &w, int *scratch) {
   __shared__ int s_np;
   int *piece = scratch;              // [2 * 192] start, end
   int *pdelta = scratch + 2 * 192;   // [192] slot - storage index, or NOSLOT
@@ -674,22 +682,50 @@ __device__ void make_window(const SlotDev &S, int lt, Window &w, int *scratch) {
 __device__ __forceinline__ void stage_window(const int *wt, gcdouble X, gcdouble Y, gcdouble Z,
                                              double *sx, double *sy, double *sz) {
   // the intervals fill slots 0 .. total-1 in order: thread t takes slots
-  // t, t + TILE, ... and walks the interval table forward (all loads of a
-  // thread are independent, so they are in flight together)
+  // t, t + TILE, ... (at most SPT of them) and walks the interval table
+  // forward.  The source indices are found first; the loads then go out in
+  // two batches, each wholly issued before its LDS writes, so a thread waits
+  // for memory twice.
+  constexpr int SPT = (WCAP + TILE - 1) / TILE, B0 = (SPT + 1) / 2;
   const int nint = wt[0];
   if (nint <= 0) return;
   const int total = wt[3 * nint] + wt[3 * nint - 1];
+  int src[SPT];
   int q = 0, end = wt[2];
-  for (int sl = threadIdx.x; sl < total; sl += TILE) {
-    while (sl >= end) {
-      ++q;
-      end = wt[3 * q + 3] + wt[3 * q + 2];
+#pragma unroll
+  for (int u = 0; u < SPT; ++u) {
+    const int sl = threadIdx.x + u * TILE;
+    src[u] = -1;
+    if (sl < total) {
+      while (sl >= end) {
+        ++q;
+        end = wt[3 * q + 3] + wt[3 * q + 2];
+      }
+      src[u] = wt[3 * q + 1] + (sl - wt[3 * q + 3]);
     }
-    const int j = wt[3 * q + 1] + (sl - wt[3 * q + 3]);
-    sx[sl] = X[j];
-    sy[sl] = Y[j];
-    sz[sl] = Z[j];
   }
+  auto batch = [&](auto first, auto count) {
+    constexpr int U0 = decltype(first)::value, NU = decltype(count)::value;
+    double bx[NU], by[NU], bz[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int j = max(src[U0 + u], 0);  // a slot beyond the window reads atom 0, unstored
+      bx[u] = X[j];
+      by[u] = Y[j];
+      bz[u] = Z[j];
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if (src[U0 + u] >= 0) {
+        const int sl = threadIdx.x + (U0 + u) * TILE;
+        sx[sl] = bx[u];
+        sy[sl] = by[u];
+        sz[sl] = bz[u];
+      }
+    }
+  };
+  batch(std::integral_constant<int, 0>{}, std::integral_constant<int, B0>{});
+  batch(std::integral_constant<int, B0>{}, std::integral_constant<int, SPT - B0>{});
 }
 
 // 27-cell traversal over the sorted atoms (offsets z-major, x fastest;
@@ -702,7 +738,7 @@ __device__ __forceinline__ void stage_window(const int *wt, gcdouble X, gcdouble
 // accumulates the forces of pairs with r^2 < r_c^2.  Positions were wrapped
 // by the sort, so they are read as stored.
 template <typename R>
-__device__ __forceinline__ int traverse_sorted(const SlotDev &S, int i, int ci, gcdouble X,
+__device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble X,
                                                gcdouble Y, gcdouble Z, const Window &w,
                                                const double *sx, const double *sy,
                                                const double *sz, double xi, double yi,
@@ -798,7 +834,7 @@ __device__ __forceinline__ int traverse_sorted(const SlotDev &S, int i, int ci, 
 // current step, unsorted since the last rebuild).  Used for an atom whose
 // neighbour list overflowed its capacity at the last build: forces only.
 template <typename R>
-__device__ void traverse_rows(const SlotDev &S, int set, int i, int ci, gcdouble X, gcdouble Y,
+__device__ void traverse_rows(SlotC &S, int set, int i, int ci, gcdouble X, gcdouble Y,
                               gcdouble Z, double xi, double yi, double zi, Acc<R> &a) {
   const int G = S.G;
   const double L = S.L, halfL = S.halfL, rc2 = S.rc2;
@@ -857,7 +893,7 @@ __device__ __forceinline__ void list_pair(Acc<R> &a, uint32_t e, double xi, doub
 }
 
 template <typename R>
-__device__ void step_tile(const SlotDev &S, CtlDev &C, int lt, int64_t k, int mode, bool cells,
+__device__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k, int mode, bool cells,
                           bool build, bool last) {
   const int i = lt * TILE + threadIdx.x;
   const bool act = i < S.n;
@@ -879,6 +915,9 @@ __device__ void step_tile(const SlotDev &S, CtlDev &C, int lt, int64_t k, int mo
   double xi = 0, yi = 0, zi = 0, v[3] = {0.0, 0.0, 0.0};
   int m = 0, ci = 0;
   uint32_t e[NE];
+  // the window table first: the staging waits for it, not for the rest
+  int wtv = 0;
+  if (list && threadIdx.x < WSTRIDE) wtv = gp((const int32_t *)S.win)[lt * WSTRIDE + threadIdx.x];
   if (act) {
     xi = X[i];
     yi = Y[i];
@@ -900,8 +939,7 @@ __device__ void step_tile(const SlotDev &S, CtlDev &C, int lt, int64_t k, int mo
   if (cells) {
     make_window(S, lt, win, (int *)sx);
   } else if (list) {
-    if (threadIdx.x < WSTRIDE)
-      win.wt[threadIdx.x] = gp((const int32_t *)S.win)[lt * WSTRIDE + threadIdx.x];
+    if (threadIdx.x < WSTRIDE) win.wt[threadIdx.x] = wtv;
     __syncthreads();
   }
   if (cells || list) {
@@ -1099,7 +1137,7 @@ __global__ __launch_bounds__(TILE, 4) void k_step(Tables T, int s, int mode, int
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
     const int r = T.tile_rep[t];
     if (only >= 0 && r != only) continue;
-    const SlotDev &S0 = T.slots[2 * r];
+    SlotC &S0 = slot(T, 2 * r);
     if (S0.fp64 != (sizeof(R) == 8)) continue;  // the other precision's kernel
     CtlDev &C = T.ctl[r];
     int64_t k;
@@ -1124,7 +1162,7 @@ __global__ __launch_bounds__(TILE, 4) void k_step(Tables T, int s, int mode, int
     // stop at an error of an earlier step; one latched by this launch (while
     // binning r(k+1), err_step = k + 1) must not stop the other workgroups
     if (C.err != 0 && C.err_step <= k) continue;
-    const SlotDev &S = T.slots[2 * r + var];
+    SlotC &S = slot(T, 2 * r + var);
     const int lt = t - S.tile_off;
     step_tile<R>(S, C, lt, k, mode, cells, build, last);
     if (mode == MODE_STEP && lt == 0 && threadIdx.x == 0)
@@ -1140,7 +1178,7 @@ __global__ void k_replay_end(Tables T, int K) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= T.nslots) return;
   CtlDev &C = T.ctl[r];
-  if (T.slots[2 * r].n <= 0) return;
+  if (slot(T, 2 * r).n <= 0) return;
   if (C.base >= C.target && C.done >= C.target) return;
   int64_t done = C.base + K < C.target ? C.base + K : C.target;
   if (C.err != 0) done = C.err_step - 1 < done ? C.err_step - 1 : done;
@@ -1166,8 +1204,8 @@ __global__ void k_set_target(Tables T, int slot, long long target) {
 __global__ __launch_bounds__(TILE) void k_props(Tables T, int only) {
   const int r = blockIdx.x;
   if (r >= T.nslots || (only >= 0 && r != only)) return;
-  if (T.slots[2 * r].n <= 0) return;
-  const SlotDev &S = slot_held(T, r);
+  if (slot(T, 2 * r).n <= 0) return;
+  SlotC &S = slot_held(T, r);
   CtlDev &C = T.ctl[r];
   __shared__ double sh[TILE][6];
   double ke = 0, vm = 0, pe = 0, vir = 0, sm = 0, mm = 0;
@@ -1222,8 +1260,8 @@ __global__ __launch_bounds__(TILE) void k_insert(Tables T, int wrap_store, int o
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
     const int r = T.tile_rep[t];
     if (only >= 0 && r != only) continue;
-    if (T.slots[2 * r].n <= 0) continue;
-    const SlotDev &S = slot_held(T, r);
+    if (slot(T, 2 * r).n <= 0) continue;
+    SlotC &S = slot_held(T, r);
     CtlDev &C = T.ctl[r];
     const int i = (t - S.tile_off) * TILE + threadIdx.x;
     if (i >= S.n) continue;
@@ -1245,7 +1283,7 @@ __global__ __launch_bounds__(TILE) void k_clear_set(Tables T, int only) {
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nct; t += gridDim.x) {
     const int r = T.ctile_rep[t];
     if (only >= 0 && r != only) continue;
-    const SlotDev &S = T.slots[2 * r];
+    SlotC &S = slot(T, 2 * r);
     const CtlDev &C = T.ctl[r];
     const int set = (int)mod3(cur_state(C));
     const int lt = t - S.ctile_off;
