@@ -55,6 +55,12 @@ typedef const __attribute__((address_space(4))) SlotDev SlotC;
 __device__ __forceinline__ SlotC &slot(const Tables &T, int idx) {
   return *(SlotC *)(T.slots + idx);
 }
+// The same view of other host-written tables, and of control words that a
+// kernel reads while no workgroup of the same launch writes them.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *cview(const T *p) {
+  return (const __attribute__((address_space(4))) T *)p;
+}
 
 // Workgroups go to the 8 XCDs round-robin; renumber them so that each XCD
 // walks a contiguous range of tiles and neighbouring atoms share an L2.
@@ -1133,35 +1139,46 @@ __device__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k, int mode, bool
 template <typename R>
 __global__ __launch_bounds__(TILE, 4) void k_step(Tables T, int s, int mode, int force_build,
                                                int only) {
-  const int nt = T.hdr[HDR_NTILES];
+  const int nt = cview(T.hdr)[HDR_NTILES];
+  // what a workgroup decides per replica is launch-invariant: it is worked
+  // out once for a run of consecutive tiles of one replica (every tile, for
+  // a single system).  The control words read here are written by earlier
+  // launches only (this launch writes other ring slots and err_step > k).
+  int rc = -1, var = 0;
+  int64_t k = 0;
+  bool skip = true, last = false, cells = false, build = false;
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
-    const int r = T.tile_rep[t];
-    if (only >= 0 && r != only) continue;
-    SlotC &S0 = slot(T, 2 * r);
-    if (S0.fp64 != (sizeof(R) == 8)) continue;  // the other precision's kernel
-    CtlDev &C = T.ctl[r];
-    int64_t k;
-    int var;
-    bool last = false, cells, build;
-    if (mode == MODE_STEP) {
-      k = C.base + s + 1;
-      if (k > C.target) continue;
-      last = k == C.target;
-      var = C.var_ring[mod3(k - 1)];
-      // k_sort of this step decided, and if so gathered r(k) into the other variant
-      cells = C.rb_ring[mod3(k)] != 0;
-      build = cells && !S0.cell_only;
-      if (cells) var ^= 1;
-    } else {
-      if (!C.clean) continue;
-      k = C.done;
-      var = C.var_ring[mod3(k)];
-      build = !S0.cell_only && (force_build || mode == MODE_BUILD);
-      cells = build || S0.cell_only;
+    const int r = cview(T.tile_rep)[t];
+    if (r != rc) {
+      rc = r;
+      skip = true;
+      SlotC &S0 = slot(T, 2 * r);
+      auto &C = *cview(T.ctl + r);
+      if ((only >= 0 && r != only) || S0.fp64 != (sizeof(R) == 8)) continue;
+      last = false;
+      if (mode == MODE_STEP) {
+        k = C.base + s + 1;
+        if (k > C.target) continue;
+        last = k == C.target;
+        var = C.var_ring[mod3(k - 1)];
+        // k_sort of this step decided, and if so gathered r(k) into the other variant
+        cells = C.rb_ring[mod3(k)] != 0;
+        build = cells && !S0.cell_only;
+        if (cells) var ^= 1;
+      } else {
+        if (!C.clean) continue;
+        k = C.done;
+        var = C.var_ring[mod3(k)];
+        build = !S0.cell_only && (force_build || mode == MODE_BUILD);
+        cells = build || S0.cell_only;
+      }
+      // stop at an error of an earlier step; one latched by this launch
+      // (while binning r(k+1), err_step = k + 1) must not stop the others
+      if (C.err != 0 && C.err_step <= k) continue;
+      skip = false;
     }
-    // stop at an error of an earlier step; one latched by this launch (while
-    // binning r(k+1), err_step = k + 1) must not stop the other workgroups
-    if (C.err != 0 && C.err_step <= k) continue;
+    if (skip) continue;
+    CtlDev &C = T.ctl[r];
     SlotC &S = slot(T, 2 * r + var);
     const int lt = t - S.tile_off;
     step_tile<R>(S, C, lt, k, mode, cells, build, last);
