@@ -165,7 +165,7 @@ __device__ __forceinline__ void latch_error(CtlDev &C, int bits, int64_t step) {
 // Cell and layer assignment of one atom (Secs. 2.2, 2.4): the atom's cell
 // from its wrapped coordinates, a layer slot from the cell's occupancy
 // counter (atomic), the row entry, or the set's overflow list beyond hcap.
-__device__ void bin_atom(SlotC &S, CtlDev &C, int set, int i, double x, double y,
+__device__ __forceinline__ void bin_atom(SlotC &S, CtlDev &C, int set, int i, double x, double y,
                          double z, int64_t step) {
   // Called by a prefix of the lanes of a wave (the active atoms of a tile).
   int bad = 0;
@@ -357,22 +357,40 @@ __global__ void k_kick_end(Tables T) {
 __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int only) {
   __shared__ int s_red[4];
   __shared__ int s_wsum[4];
-  const int nct = T.hdr[HDR_NCTILES];
+  const int nct = cview(T.hdr)[HDR_NCTILES];
+  // the decision for a replica is launch-invariant: a workgroup works it out
+  // once for a run of consecutive cell tiles of one replica
+  int rc = -1, var = 0;
+  int64_t k = 0;
+  bool skip = true, rebuild = false;
+  double d1 = 0.0;
   for (int t = xcd_block(blockIdx.x, gridDim.x); t < nct; t += gridDim.x) {
-    const int r = T.ctile_rep[t];
-    if (only >= 0 && r != only) continue;
+    const int r = cview(T.ctile_rep)[t];
     CtlDev &C = T.ctl[r];
     SlotC &S0 = slot(T, 2 * r);
-    int64_t k;
-    int var;
+    if (r != rc) {
+      rc = r;
+      skip = true;
+      if (only >= 0 && r != only) continue;
+      if (mode == MODE_STEP) {
+        k = C.base + s + 1;
+        if (k > C.target) continue;
+        if (C.err != 0 && C.err_step <= k) continue;
+        var = C.var_ring[mod3(k - 1)];
+        rebuild = true;
+        d1 = 0.0;
+        if (!S0.cell_only) rebuild = rebuild_at(S0, C, k, &d1);
+      } else {
+        if (!C.clean) continue;
+        k = C.done;
+        if (C.err != 0 && C.err_step <= k) continue;
+        var = C.var_ring[mod3(k)];
+        rebuild = true;
+      }
+      skip = false;
+    }
+    if (skip) continue;
     if (mode == MODE_STEP) {
-      k = C.base + s + 1;
-      if (k > C.target) continue;
-      if (C.err != 0 && C.err_step <= k) continue;
-      var = C.var_ring[mod3(k - 1)];
-      bool rebuild = true;
-      double d1 = 0.0;
-      if (!S0.cell_only) rebuild = rebuild_at(S0, C, k, &d1);
       if (t == S0.ctile_off && threadIdx.x == 0) {
         // the one writer of these ring slots for step k
         C.rb_ring[mod3(k)] = rebuild ? 1 : 0;
@@ -382,11 +400,6 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
         }
       }
       if (!rebuild) continue;
-    } else {
-      if (!C.clean) continue;
-      k = C.done;
-      if (C.err != 0 && C.err_step <= k) continue;
-      var = C.var_ring[mod3(k)];
     }
     SlotC &S = slot(T, 2 * r + var);
     SlotC &D = slot(T, 2 * r + (var ^ 1));
@@ -398,8 +411,20 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
 
     // atoms in the earlier tiles
     const auto TC = gp((const int32_t *)S.tcnt[set]);
+    // (eight independent loads in flight per thread: integer sums, so the
+    // grouping does not change the result)
     int pre = 0;
-    for (int q = threadIdx.x; q < lt; q += TILE) pre += TC[q];
+    {
+      int q = threadIdx.x;
+      for (; q + 7 * TILE < lt; q += 8 * TILE) {
+        int p8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p8[u] = TC[q + u * TILE];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pre += p8[u];
+      }
+      for (; q < lt; q += TILE) pre += TC[q];
+    }
     for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
     if (l == 0) s_red[w] = pre;
 
@@ -755,7 +780,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   const int mcap = S.mcap;
   const auto Wc = gp(S.W) + i;
   const size_t np = (size_t)S.npad;
-  const auto CS = gp((const int32_t *)S.cs);
+  const auto CS = cview((const int32_t *)S.cs);  // written by the sort, read-only here
   const int cx = ci % G, cy = (ci / G) % G, cz = ci / (G * G);
   const int sr = ci / G - w.rf;  // source row of the atom within the tile
   const bool whole = w.whole, rows = !whole && w.wt[0] >= 0;
@@ -765,6 +790,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   // flight together), else each lane reads where its piece lives
   auto candidates = [&](auto from_lds, int lo, int hi, int delta, uint32_t code, double bx,
                         double by, double bz) {
+    // ALL_LDS also means that no lane of the wave applies an image shift
     constexpr bool ALL_LDS = decltype(from_lds)::value;
     const bool lds = ALL_LDS || delta != NOSLOT;
     for (int j0 = lo; j0 < hi; j0 += 4) {
@@ -786,9 +812,12 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + u;
         if (j >= hi || j == i) continue;
-        const double dx = (xi - xj[u]) + bx;
-        const double dy = (yi - yj[u]) + by;
-        const double dz = (zi - zj[u]) + bz;
+        double dx = xi - xj[u], dy = yi - yj[u], dz = zi - zj[u];
+        if (!ALL_LDS) {
+          dx = dx + bx;
+          dy = dy + by;
+          dz = dz + bz;
+        }
         const double s = (dx * dx + dy * dy) + dz * dz;
         if (s < rn2) {
           if (build) {
@@ -802,16 +831,36 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
     }
   };
   auto range = [&](int lo, int hi, int delta, uint32_t code, double bx, double by, double bz) {
-    if (__ballot(delta == NOSLOT && lo < hi) == 0)
+    if (__ballot(lo < hi && (delta == NOSLOT || code != 0)) == 0)
       candidates(std::true_type{}, lo, hi, delta, code, bx, by, bz);
     else
       candidates(std::false_type{}, lo, hi, delta, code, bx, by, bz);
   };
+  // storage bounds of row q: the x-neighbours that do not wrap (one
+  // contiguous range) and the one wrapped cell, visited first when cx == 0
+  // (cell G-1) and last when cx == G-1 (cell 0).  The bounds of the next row
+  // are loaded before the current one is visited, so their latency is hidden
+  // behind it.
+  const int xm0 = max(cx - 1, 0), xm1 = min(cx + 2, G);
+  const int xe = cx == 0 ? G - 1 : 0;
+  const bool wlo = cx == 0, whi = cx == G - 1 && cx != 0;
+  auto bounds = [&](int q, int (&b)[4]) {
+    const int nz = cz + q / 3 - 1, ny = cy + q % 3 - 1;
+    const int row = ((nz < 0 ? nz + G : nz >= G ? nz - G : nz) * G +
+                     (ny < 0 ? ny + G : ny >= G ? ny - G : ny)) * G;
+    b[0] = CS[row + xm0];
+    b[1] = CS[row + xm1];
+    b[2] = CS[row + xe];
+    b[3] = CS[row + xe + 1];
+  };
+  int cur[4], nxt[4];
+  bounds(0, cur);
+#pragma unroll 1
   for (int q = 0; q < 9; ++q) {
+    if (q < 8) bounds(q + 1, nxt);
     uint32_t iz, iy;
-    const int nz = wrap_cell(cz + q / 3 - 1, G, &iz);
-    const int ny = wrap_cell(cy + q % 3 - 1, G, &iy);
-    const int row = (nz * G + ny) * G;
+    wrap_cell(cz + q / 3 - 1, G, &iz);
+    wrap_cell(cy + q % 3 - 1, G, &iy);
     const double by = img_shift(iy, L), bz = img_shift(iz, L);
     const uint32_t cyz = ((iy << 2) | (iz << 4)) << J_BITS;
     int dm = NOSLOT, d0 = NOSLOT, dg = NOSLOT;
@@ -823,15 +872,11 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
       d0 = w.dl[e + 1];
       dg = w.dl[e + 2];
     }
-    if (cx > 0 && cx < G - 1) {
-      range(CS[row + cx - 1], CS[row + cx + 2], dm, cyz, 0.0, by, bz);
-    } else if (cx == 0) {
-      range(CS[row + G - 1], CS[row + G], dg, cyz | (1u << J_BITS), L, by, bz);
-      range(CS[row], CS[row + 2], dm, cyz, 0.0, by, bz);
-    } else {
-      range(CS[row + G - 2], CS[row + G], dm, cyz, 0.0, by, bz);
-      range(CS[row], CS[row + 1], d0, cyz | (2u << J_BITS), -L, by, bz);
-    }
+    range(wlo ? cur[2] : 0, wlo ? cur[3] : 0, dg, cyz | (1u << J_BITS), L, by, bz);
+    range(cur[0], cur[1], dm, cyz, 0.0, by, bz);
+    range(whi ? cur[2] : 0, whi ? cur[3] : 0, d0, cyz | (2u << J_BITS), -L, by, bz);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
   }
   return m;
 }
@@ -899,7 +944,7 @@ __device__ __forceinline__ void list_pair(Acc<R> &a, uint32_t e, double xi, doub
 }
 
 template <typename R>
-__device__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k, int mode, bool cells,
+__device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k, int mode, bool cells,
                           bool build, bool last) {
   const int i = lt * TILE + threadIdx.x;
   const bool act = i < S.n;
