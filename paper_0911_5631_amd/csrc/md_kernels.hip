@@ -449,7 +449,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     if (c < S.ncell && cnt > 0) {
       const int n = S.n;
       const double L = S.L, halfL = S.halfL;
-      visit_cell(S, set, c, cnt, [&](int a, int q) {
+      auto move = [&](int a, int q) {
         const int p = base + q;
         if (p >= n || a < 0 || a >= n) return;  // inconsistent counts: never expected
 #pragma unroll
@@ -459,7 +459,48 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
         }
         gp(D.id)[p] = gp(S.id)[a];
         gp(D.cell)[p] = c;
-      });
+      };
+      if (cnt <= 8 && cnt <= S.hcap) {
+        // the usual cell: its members ordered by a sorting network, then
+        // moved four at a time with every load of a batch issued before
+        // its stores
+        const int32_t *row = S.H[set] + (size_t)c * S.hcap;
+        int v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = e < cnt ? gp(row)[e] : INT_MAX;
+        sort8(v);
+#pragma unroll
+        for (int b = 0; b < 8; b += 4) {
+          if (b < cnt) {
+            double pv[4][6];
+            int idv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int a = min(max(b + u < cnt ? v[b + u] : v[0], 0), n - 1);
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                pv[u][d] = gp(S.P[pb][d])[a];
+                pv[u][3 + d] = gp(S.V[vb][d])[a];
+              }
+              idv[u] = gp(S.id)[a];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int p = base + b + u, a = v[b + u];
+              if (b + u >= cnt || p >= n || a < 0 || a >= n) continue;
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                gp(D.P[pb][d])[p] = wrap1(pv[u][d], L, halfL);
+                gp(D.V[vb][d])[p] = pv[u][3 + d];
+              }
+              gp(D.id)[p] = idv[u];
+              gp(D.cell)[p] = c;
+            }
+          }
+        }
+      } else {
+        visit_cell(S, set, c, cnt, move);
+      }
     }
     __syncthreads();
   }
