@@ -533,9 +533,12 @@ __device__ __forceinline__ double recip(double s) { return 1.0 / s; }
 // Pair force and energy of Eq. (1) with the soft-sphere shift: for r^2 = s,
 // f = 48 r^-8 (r^-6 - 1/2) (force on i is f d), u = 4 r^-6 (r^-6 - 1) + shift.
 // FP32 uses the hardware reciprocal (1 ulp).
+// The energy and virial terms are summed only when ENERGY is set (a
+// wave-uniform flag: the steps whose per-atom sums somebody reads); the
+// force arithmetic is the same either way.
 template <typename R>
 __device__ __forceinline__ void pair_accum(Acc<R> &a, double dx, double dy, double dz, double s,
-                                           R ushift) {
+                                           R ushift, bool energy) {
   const R sr = (R)s;
   const R rri = recip(sr);
   const R rri3 = rri * rri * rri;
@@ -543,8 +546,10 @@ __device__ __forceinline__ void pair_accum(Acc<R> &a, double dx, double dy, doub
   a.fx += f * (R)dx;
   a.fy += f * (R)dy;
   a.fz += f * (R)dz;
-  a.u += (R)4 * rri3 * (rri3 - (R)1) + ushift;
-  a.w += f * sr;
+  if (energy) {
+    a.u += (R)4 * rri3 * (rri3 - (R)1) + ushift;
+    a.w += f * sr;
+  }
 }
 
 // Image shift code: 2 bits per dimension, 0 -> 0, 1 -> +L, 2 -> -L.
@@ -866,7 +871,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
             if (m < mcap) Wc[(size_t)m * np] = (int32_t)(idx | code);
             ++m;
           }
-          if (force && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
+          if (force && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, true);
         }
       }
     }
@@ -945,7 +950,7 @@ __device__ void traverse_rows(SlotC &S, int set, int i, int ci, gcdouble X, gcdo
       const double dy = (yi - wrap1(Y[j], L, halfL)) + by;
       const double dz = (zi - wrap1(Z[j], L, halfL)) + bz;
       const double s = (dx * dx + dy * dy) + dz * dz;
-      if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
+      if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, true);
     });
   }
 }
@@ -972,7 +977,7 @@ __device__ __forceinline__ void entry_pos(uint32_t e, gcdouble X, gcdouble Y, gc
 template <typename R, bool SHIFT>
 __device__ __forceinline__ void list_pair(Acc<R> &a, uint32_t e, double xi, double yi, double zi,
                                           double xj, double yj, double zj, double L, double rc2,
-                                          R ushift) {
+                                          R ushift, bool energy) {
   double dx = xi - xj, dy = yi - yj, dz = zi - zj;
   if (SHIFT) {
     const uint32_t code = e >> J_BITS;
@@ -981,7 +986,7 @@ __device__ __forceinline__ void list_pair(Acc<R> &a, uint32_t e, double xi, doub
     dz = dz + img_shift((code >> 4) & 3u, L);
   }
   const double s = (dx * dx + dy * dy) + dz * dz;
-  if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift);
+  if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
 }
 
 template <typename R>
@@ -1048,6 +1053,7 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
       if (m <= S.mcap) {
         const double rc2 = S.rc2;
         const R ushift = (R)S.ushift;
+        const bool energy = mode != MODE_STEP || last;
         // entries in order, four at a time (their coordinate reads together);
         // a group without image codes anywhere in the wave skips the shifts
         auto group = [&](uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
@@ -1070,17 +1076,19 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
           if (__ballot(((e0 | e1 | e2 | e3) >> J_BITS) != 0) == 0) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              list_pair<R, false>(a, eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2, ushift);
+              list_pair<R, false>(a, eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2, ushift,
+                                  energy);
           } else {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              list_pair<R, true>(a, eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2, ushift);
+              list_pair<R, true>(a, eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2, ushift,
+                                 energy);
           }
         };
         auto single = [&](uint32_t e0) {
           double xj, yj, zj;
           entry_pos(e0, X, Y, Z, sx, sy, sz, xj, yj, zj);
-          list_pair<R, true>(a, e0, xi, yi, zi, xj, yj, zj, L, rc2, ushift);
+          list_pair<R, true>(a, e0, xi, yi, zi, xj, yj, zj, L, rc2, ushift, energy);
         };
         int q = 0;
 #pragma unroll
