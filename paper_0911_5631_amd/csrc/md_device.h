@@ -30,7 +30,8 @@ constexpr int TILE = 256;          // atoms per tile (one workgroup of 4 wave64)
 constexpr int CTILE = 256;         // cells per sort tile (one per thread)
 // Neighbour entry (32 bits): bits 0-24 an index, bit 25 (GFLAG) set when the
 // index is a storage index and clear when it is a slot of the tile's LDS
-// window, bits 26-31 the periodic image code (2 bits per dimension).
+// window, bits 26-31 the periodic image code (2 bits per dimension, x
+// lowest: 0 none, 1 +L, 3 -L).
 constexpr int J_BITS = 26;         // image code starts here
 constexpr int IDX_BITS = 25;
 constexpr uint32_t IDX_MASK = (1u << IDX_BITS) - 1;

@@ -552,7 +552,8 @@ __device__ __forceinline__ void pair_accum(Acc<R> &a, double dx, double dy, doub
   }
 }
 
-// Image shift code: 2 bits per dimension, 0 -> 0, 1 -> +L, 2 -> -L.
+// Image shift code: 2 bits per dimension, a two's-complement multiple of L
+// (0 -> 0, 1 -> +L, 3 -> -L).
 __device__ __forceinline__ double img_shift(uint32_t code, double L) {
   return code == 0 ? 0.0 : (code == 1 ? L : -L);
 }
@@ -561,7 +562,7 @@ __device__ __forceinline__ double img_shift(uint32_t code, double L) {
 // and the image code of the atoms found there.
 __device__ __forceinline__ int wrap_cell(int c, int G, uint32_t *code) {
   if (c >= G) {
-    *code = 2;
+    *code = 3;
     return c - G;
   }
   if (c < 0) {
@@ -920,7 +921,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
     }
     range(wlo ? cur[2] : 0, wlo ? cur[3] : 0, dg, cyz | (1u << J_BITS), L, by, bz);
     range(cur[0], cur[1], dm, cyz, 0.0, by, bz);
-    range(whi ? cur[2] : 0, whi ? cur[3] : 0, d0, cyz | (2u << J_BITS), -L, by, bz);
+    range(whi ? cur[2] : 0, whi ? cur[3] : 0, d0, cyz | (3u << J_BITS), -L, by, bz);
 #pragma unroll
     for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
   }
@@ -972,21 +973,22 @@ __device__ __forceinline__ void entry_pos(uint32_t e, gcdouble X, gcdouble Y, gc
   }
 }
 
-// One neighbour-list entry e (index + image code) of atom i.  SHIFT = false
-// when no entry of the wave's current group carries an image code.
+// One neighbour-list entry e (index + image code) of atom i, counted when ok.
+// SHIFT = false when no entry of the wave's current group carries an image
+// code.
 template <typename R, bool SHIFT>
-__device__ __forceinline__ void list_pair(Acc<R> &a, uint32_t e, double xi, double yi, double zi,
-                                          double xj, double yj, double zj, double L, double rc2,
-                                          R ushift, bool energy) {
+__device__ __forceinline__ void list_pair(Acc<R> &a, bool ok, uint32_t e, double xi, double yi,
+                                          double zi, double xj, double yj, double zj, double L,
+                                          double rc2, R ushift, bool energy) {
   double dx = xi - xj, dy = yi - yj, dz = zi - zj;
   if (SHIFT) {
-    const uint32_t code = e >> J_BITS;
-    dx = dx + img_shift(code & 3u, L);
-    dy = dy + img_shift((code >> 2) & 3u, L);
-    dz = dz + img_shift((code >> 4) & 3u, L);
+    // each 2-bit field sign-extended is the multiple of L (exact products)
+    dx = dx + (double)((int32_t)(e << (32 - J_BITS - 2)) >> 30) * L;
+    dy = dy + (double)((int32_t)(e << (32 - J_BITS - 4)) >> 30) * L;
+    dz = dz + (double)((int32_t)e >> 30) * L;
   }
   const double s = (dx * dx + dy * dy) + dz * dz;
-  if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
+  if (ok && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
 }
 
 template <typename R>
@@ -1054,12 +1056,18 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
         const double rc2 = S.rc2;
         const R ushift = (R)S.ushift;
         const bool energy = mode != MODE_STEP || last;
-        // entries in order, four at a time (their coordinate reads together);
-        // a group without image codes anywhere in the wave skips the shifts
-        auto group = [&](uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
-          const uint32_t eg[4] = {e0, e1, e2, e3};
+        // entries in order, four at a time (their coordinate reads together),
+        // for as long as any lane of the wave has some left: a lane past its
+        // length takes the group with no effect, so the wave runs max(m)/4
+        // groups whatever the spread of m.  A group without image codes
+        // anywhere in the wave skips the shifts.
+        auto group = [&](int q0, uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
+          const bool ok[4] = {q0 < m, q0 + 1 < m, q0 + 2 < m, q0 + 3 < m};
+          const uint32_t eg[4] = {ok[0] ? e0 : 0u, ok[1] ? e1 : 0u, ok[2] ? e2 : 0u,
+                                  ok[3] ? e3 : 0u};
+          const uint32_t any = (eg[0] | eg[1]) | (eg[2] | eg[3]);
           double xj[4], yj[4], zj[4];
-          if (__ballot(((e0 | e1 | e2 | e3) & GFLAG) != 0) == 0) {
+          if (__ballot((any & GFLAG) != 0) == 0) {
             // the usual case: every entry of the wave is a window slot
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -1073,38 +1081,27 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
             for (int u = 0; u < 4; ++u)
               entry_pos(eg[u], X, Y, Z, sx, sy, sz, xj[u], yj[u], zj[u]);
           }
-          if (__ballot(((e0 | e1 | e2 | e3) >> J_BITS) != 0) == 0) {
+          if (__ballot((any >> J_BITS) != 0) == 0) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              list_pair<R, false>(a, eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2, ushift,
-                                  energy);
+              list_pair<R, false>(a, ok[u], eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2,
+                                  ushift, energy);
           } else {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              list_pair<R, true>(a, eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2, ushift,
-                                 energy);
+              list_pair<R, true>(a, ok[u], eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2,
+                                 ushift, energy);
           }
         };
-        auto single = [&](uint32_t e0) {
-          double xj, yj, zj;
-          entry_pos(e0, X, Y, Z, sx, sy, sz, xj, yj, zj);
-          list_pair<R, true>(a, e0, xi, yi, zi, xj, yj, zj, L, rc2, ushift, energy);
-        };
-        int q = 0;
 #pragma unroll
         for (int g = 0; g < NE / 4; ++g)
-          if (q + 4 <= m) {
-            group(e[4 * g], e[4 * g + 1], e[4 * g + 2], e[4 * g + 3]);
-            q += 4;
-          }
+          if (__ballot(4 * g < m) != 0)
+            group(4 * g, e[4 * g], e[4 * g + 1], e[4 * g + 2], e[4 * g + 3]);
+        for (int q = NE; __ballot(q < m) != 0; q += 4) {
+          uint32_t ew[4];
 #pragma unroll
-        for (int u = 0; u < NE; ++u)
-          if (u >= q && u < m) single(e[u]);
-        if (m > NE) {
-          for (; q + 4 <= m; q += 4)
-            group((uint32_t)Wc[(size_t)q * np], (uint32_t)Wc[(size_t)(q + 1) * np],
-                  (uint32_t)Wc[(size_t)(q + 2) * np], (uint32_t)Wc[(size_t)(q + 3) * np]);
-          for (; q < m; ++q) single((uint32_t)Wc[(size_t)q * np]);
+          for (int u = 0; u < 4; ++u) ew[u] = q + u < m ? (uint32_t)Wc[(size_t)(q + u) * np] : 0u;
+          group(q, ew[0], ew[1], ew[2], ew[3]);
         }
       } else {
         // the list overflowed its capacity at the last build: evaluate this
