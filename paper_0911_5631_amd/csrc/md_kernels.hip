@@ -820,7 +820,8 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
                                                gcdouble Y, gcdouble Z, const Window &w,
                                                const double *sx, const double *sy,
                                                const double *sz, double xi, double yi,
-                                               double zi, bool build, bool force, Acc<R> &a) {
+                                               double zi, bool build, bool force, bool energy,
+                                               Acc<R> &a) {
   const int G = S.G;
   const double L = S.L, rn2 = S.rn2, rc2 = S.rc2;
   const R ushift = (R)S.ushift;
@@ -872,7 +873,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
             if (m < mcap) Wc[(size_t)m * np] = (int32_t)(idx | code);
             ++m;
           }
-          if (force && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, true);
+          if (force && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
         }
       }
     }
@@ -1049,7 +1050,8 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
   Acc<R> a{(R)0, (R)0, (R)0, (R)0, (R)0};
   if (act) {
     if (cells) {
-      m = traverse_sorted<R>(S, i, ci, X, Y, Z, win, sx, sy, sz, xi, yi, zi, build, force, a);
+      m = traverse_sorted<R>(S, i, ci, X, Y, Z, win, sx, sy, sz, xi, yi, zi, build, force,
+                             mode != MODE_STEP || last, a);
       if (build) gp(S.m)[i] = m;
     } else if (list) {
       if (m <= S.mcap) {
