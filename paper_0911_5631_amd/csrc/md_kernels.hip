@@ -181,7 +181,10 @@ __device__ __forceinline__ void bin_atom(SlotC &S, CtlDev &C, int set, int i, do
   // Consecutive lanes with the same cell take their layer slots with one
   // atomic: atoms are stored in cell order, so most of a cell's atoms are
   // neighbours in a wave.
-  const int lane = threadIdx.x & 63;
+  // (the empty asm keeps the lane masks below from being hoisted out of the
+  // tile loop, where they would be held across it and spilled)
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
   const unsigned long long active = __ballot(1);
   const int na = __popcll(active);
   const int cp = __shfl_up(c, 1, 64);
