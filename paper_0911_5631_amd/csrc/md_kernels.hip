@@ -707,43 +707,84 @@ __device__ void make_window(SlotC &S, int lt, Window &w, int *scratch) {
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     const int npc = s_np;
-    int nint = 0;
     if (npc == -2) {
-      w.wt[1] = 0;
-      w.wt[2] = n;
-      w.wt[3] = 0;
-      nint = 1;
-    } else if (npc < 0) {
-      nint = -1;
-    } else {
-      int off = 0;
-      for (int p = 0; p < npc; ++p) {
-        const int s0 = piece[2 * p], len = piece[2 * p + 1] - s0;
-        if (len <= 0) {
-          pdelta[p] = 0;  // empty: no candidate ever reads it
-        } else if (off + len > WCAP) {
-          pdelta[p] = NOSLOT;
-        } else {
-          pdelta[p] = off - s0;
-          if (nint > 0 && w.wt[3 * nint - 2] + w.wt[3 * nint - 1] == s0 &&
-              w.wt[3 * nint] + w.wt[3 * nint - 1] == off) {
-            w.wt[3 * nint - 1] += len;
-          } else if (nint < NWIN) {
-            w.wt[3 * nint + 1] = s0;
-            w.wt[3 * nint + 2] = len;
-            w.wt[3 * nint + 3] = off;
-            ++nint;
-          } else {
-            pdelta[p] = NOSLOT;
-            continue;
-          }
-          off += len;
-        }
+      if (lane == 0) {
+        w.wt[0] = 1;
+        w.wt[1] = 0;
+        w.wt[2] = n;
+        w.wt[3] = 0;
       }
+    } else if (npc < 0) {
+      if (lane == 0) w.wt[0] = -1;
+    } else {
+      // Pieces take slots in list order while they fit (from the first that
+      // does not, the rest stay in global memory).  A non-empty piece that
+      // continues the previous non-empty one in storage extends its staging
+      // interval, else it opens one (at most NWIN).  Lane l holds pieces
+      // 3l .. 3l+2; offsets and interval numbers are wave prefix sums.
+      int ps[3], pe[3], ln[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const int p = 3 * lane + e;
+        ps[e] = p < npc ? piece[2 * p] : 0;
+        pe[e] = p < npc ? piece[2 * p + 1] : 0;
+        ln[e] = p < npc ? max(pe[e] - ps[e], 0) : 0;
+      }
+      auto scan = [&](int v) {  // inclusive prefix sum over the wave
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(v, o, 64);
+          if (lane >= o) v += y;
+        }
+        return v;
+      };
+      const int lsum = (ln[0] + ln[1]) + ln[2];
+      int off[3];
+      off[0] = scan(lsum) - lsum;
+      off[1] = off[0] + ln[0];
+      off[2] = off[1] + ln[1];
+      const int pe_prev = __shfl_up(pe[2], 1, 64), ln_prev = __shfl_up(ln[2], 1, 64);
+      bool fit[3], st[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const int p = 3 * lane + e;
+        const int prev_end = e == 0 ? pe_prev : pe[e - 1];
+        const bool prev_full = e == 0 ? (lane > 0 && ln_prev > 0) : ln[e - 1] > 0;
+        fit[e] = p < npc && ln[e] > 0 && off[e] + ln[e] <= WCAP;
+        st[e] = fit[e] && !(prev_full && ps[e] == prev_end);
+      }
+      const int nst = (int)st[0] + (int)st[1] + (int)st[2];
+      const int kincl = scan(nst), nstarts = __shfl(kincl, 63, 64);
+      int k[3];
+      k[0] = kincl - nst + (int)st[0] - 1;
+      k[1] = k[0] + (int)st[1];
+      k[2] = k[1] + (int)st[2];
+      bool ok[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) ok[e] = fit[e] && k[e] < NWIN;
+      // the piece after e continues e's interval?
+      const bool ok_next0 = __shfl_down((int)ok[0], 1, 64) != 0,
+                 st_next0 = __shfl_down((int)st[0], 1, 64) != 0;
+      const bool cont[3] = {ok[1] && !st[1], ok[2] && !st[2],
+                            lane < 63 && ok_next0 && !st_next0};
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const int p = 3 * lane + e;
+        if (p < npc) pdelta[p] = ln[e] == 0 ? 0 : (ok[e] ? off[e] - ps[e] : NOSLOT);
+        if (ok[e] && st[e]) {
+          w.wt[3 * k[e] + 1] = ps[e];
+          w.wt[3 * k[e] + 3] = off[e];
+        }
+        if (ok[e] && !cont[e]) w.wt[3 * k[e] + 2] = off[e] + ln[e];  // end slot
+      }
+      // (same wave, later instructions: the end slots are written) length =
+      // end - first slot
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+        if (ok[e] && st[e]) w.wt[3 * k[e] + 2] -= off[e];
+      if (lane == 0) w.wt[0] = min(nstarts, NWIN);
     }
-    w.wt[0] = nint;
   }
   __syncthreads();
   if (threadIdx.x < 64 && T != INT_MAX) {
