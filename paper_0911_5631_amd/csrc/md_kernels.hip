@@ -595,10 +595,11 @@ struct Window {
 // (source row, dz, dy), sorts the list by target row (bitonic, across the
 // lanes), unites the x-ranges of equal rows, and turns each row into 1-3 cell
 // pieces (cell 0 | main | cell G-1 when the x-range wraps, else one piece),
-// i.e. storage-index intervals via cell_start.  Thread 0 gives the pieces LDS
-// slots in index order up to WCAP (a piece that does not fit stays in global
-// memory) and merges adjacent ones into staging intervals.  The staging table
-// also goes to S.win for the list steps until the next sort.
+// i.e. storage-index intervals via cell_start.  Wave 0 then gives the pieces
+// LDS slots in list order while they fit in WCAP (from the first that does
+// not, pieces stay in global memory), merging storage-adjacent ones into
+// staging intervals, with wave prefix sums.  The staging table also goes to
+// S.win for the list steps until the next sort.
 __device__ void make_window(SlotC &S, int lt, Window &w, int *scratch) {
   __shared__ int s_np;
   int *piece = scratch;              // [2 * 192] start, end
