@@ -23,8 +23,9 @@
  *   - layer assignment (Sec. 2.4, first algorithm) and the cell-order
  *     reordering scan of the cell-layer matrix (Sec. 2.5, reorder algorithm),
  *     used to state what a stable cell binning must produce;
- *   - the leapfrog MD loop, steps (a)-(e), with the neighbour-list rebuild
- *     rule "cumulative maximum displacement reaches delta/2" (Sec. 2.1);
+ *   - the leapfrog MD loop, steps (a)-(e), with the neighbour list rebuilt
+ *     once the accumulated maximum displacement passes delta/2 (Sec. 2.1), and
+ *     step (f), the velocity adjustment of the equilibration period (Sec. 4);
  *   - brute-force O(N^2) definitions of the pair set and of the forces over
  *     all 27 periodic images, used to pin the cell algorithms above.
  *
@@ -754,6 +755,29 @@ int or_sim_run(or_sim *s, int64_t nsteps, double *trace)
         if (rec) rec[5] = (double)rebuilt;
     }
     return rc;
+}
+
+/* Step (f) of the loop (Sec. 2.1), as used during the equilibration period
+ * of Sec. 4: scale every velocity by one factor so that the kinetic
+ * temperature equals T.  With the centre of mass at rest the velocities carry
+ * 3 (N - 1) degrees of freedom, so the target is sum v^2 = 3 (N - 1) T.
+ * The sum is the plain sequential one.  Returns the factor (1 when there is
+ * nothing to scale: N < 2 or every velocity zero). */
+double or_sim_adjust_temp(or_sim *s, double temperature)
+{
+    loop_t *lp = &s->lp;
+    const int64_t n = lp->n;
+    double vv = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        vv += (lp->vx[i] * lp->vx[i] + lp->vy[i] * lp->vy[i]) + lp->vz[i] * lp->vz[i];
+    if (n < 2 || !(vv > 0.0)) return 1.0;
+    const double fac = sqrt(3.0 * (double)(n - 1) * temperature / vv);
+    for (int64_t i = 0; i < n; ++i) {
+        lp->vx[i] *= fac;
+        lp->vy[i] *= fac;
+        lp->vz[i] *= fac;
+    }
+    return fac;
 }
 
 /* Copy out positions, velocities, forces (n x 3, row-major, may be NULL)

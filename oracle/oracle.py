@@ -93,6 +93,8 @@ def lib():
         L.or_sim_pairs.restype = C.c_int64
         L.or_sim_pairs.argtypes = [C.c_void_p, C.c_int64, _I32, _I32, _I8]
         L.or_sim_free.argtypes = [C.c_void_p]
+        L.or_sim_adjust_temp.restype = C.c_double
+        L.or_sim_adjust_temp.argtypes = [C.c_void_p, C.c_double]
         _lib = L
     return _lib
 
@@ -321,6 +323,30 @@ class Sim:
                 return pi[:m].copy(), pj[:m].copy(), img[:m].copy()
             cap = int(m)
 
+    def adjust_temp(self, temperature: float) -> float:
+        """Step (f): scale the velocities to sum v^2 = 3 (N - 1) T; returns
+        the factor."""
+        return float(lib().or_sim_adjust_temp(self._h, float(temperature)))
+
+    def equilibrate_run(self, nsteps: int, temperature: float, equil_steps: int = 500,
+                        interval: int = 20) -> np.ndarray:
+        """``run`` with the equilibration of Sec. 4 folded in: after step k
+        (absolute count) with k <= equil_steps and k a multiple of interval,
+        the velocities are adjusted to T.  Properties of step k in the trace
+        are those of (e), before the adjustment."""
+        out = []
+        done = int(self.state()[3].step)
+        end = done + nsteps
+        while done < end:
+            nxt = end
+            if done < equil_steps:
+                nxt = min(end, (done // interval + 1) * interval)
+            out.append(self.run(nxt - done))
+            done = nxt
+            if done <= equil_steps and done % interval == 0:
+                self.adjust_temp(temperature)
+        return np.concatenate(out) if out else np.zeros((0, len(TRACE_FIELDS)))
+
     def close(self):
         if getattr(self, "_h", None):
             lib().or_sim_free(self._h)
@@ -328,3 +354,17 @@ class Sim:
 
     def __del__(self):
         self.close()
+
+
+def block_means(trace: np.ndarray, n_atoms: int, first: int, last: int) -> dict:
+    """Means over steps first..last (1-based, inclusive) of a trace that starts
+    at step 1: per-atom kinetic, potential and total energy and virial, and
+    the mean neighbour-list length per atom (twice the pairs per atom, the
+    quantity the paper tabulates as neighbours per atom).  Sec. 4 averages
+    properties over blocks of 1000 steps."""
+    rows = trace[first - 1:last]
+    ke = rows[:, 0].mean() / n_atoms
+    pe = rows[:, 1].mean() / n_atoms
+    return {"steps": len(rows), "ke_per_atom": ke, "pe_per_atom": pe,
+            "etot_per_atom": ke + pe, "virial_per_atom": rows[:, 2].mean() / n_atoms,
+            "nebr_per_atom": 2.0 * rows[:, 4].mean() / n_atoms}
