@@ -19,7 +19,9 @@
  *   (d) second half-step velocity update;
  *   (e) kinetic energy, maximum speed and the rebuild decision: the list is
  *       rebuilt when the accumulated sum of vmax*dt exceeds delta/2
- *       (Sec. 2.1).
+ *       (Sec. 2.1);
+ *   (f) during equilibration, the velocity adjustment (md_adjust_temp);
+ *       properties averaged over blocks of steps (md_block_begin/end).
  * With shell == 0 the library runs the plain cell method instead (Sec. 2.1):
  * every step re-bins and evaluates forces straight from the 27 neighbouring
  * cells, with no stored list.
@@ -117,6 +119,17 @@ typedef struct {
     int32_t cells_per_edge; /* G */
 } md_props_t;
 
+/* Means over the steps of a block (md_block_begin .. md_block_end). */
+typedef struct {
+    int64_t steps;          /* steps completed inside the block */
+    double ke_per_atom;     /* mean of (1/2) sum v^2 / N over those steps */
+    double pe_per_atom;     /* mean of PE / N */
+    double etot_per_atom;   /* ke_per_atom + pe_per_atom */
+    double virial_per_atom; /* mean of W / N */
+    double nebr_per_atom;   /* mean neighbour-list entries per atom (the paper's
+                               N_p / N_a; 0 in cell-list-only mode) */
+} md_block_t;
+
 typedef struct {
     void *(*alloc)(size_t bytes, void *ctx); /* device memory, >= 256-byte aligned */
     void (*free)(void *ptr, void *ctx);
@@ -175,6 +188,28 @@ md_status md_step(md_system *s, int64_t n_steps);
 /* Properties after the last completed step (or creation / md_forces).
  * Sync; returns latched device errors. */
 md_status md_props(md_system *s, md_props_t *out);
+
+/* Step (f) of the loop (Sec. 2.1), used during the equilibration period of
+ * Sec. 4 (every 20 steps for the first 500): scale every velocity of the
+ * held state by one factor so that sum v^2 = 3 (N - 1) T, T = temperature
+ * (with the centre of mass at rest 3 (N - 1) degrees of freedom remain).
+ * Call it after md_step; the factor comes from the kinetic energy of (e) of
+ * the last completed step, which the rebuild rule also keeps (the maximum
+ * speed of (e) is taken before the adjustment).  Does nothing when every
+ * velocity is zero or N < 2.  MD_ERR_INVALID_ARG unless temperature is
+ * positive and finite.  Async. */
+md_status md_adjust_temp(md_system *s, double temperature);
+
+/* Block averages (Sec. 4 evaluates its properties as means over blocks of
+ * 1000 steps).  md_block_begin starts a block at the held step: every
+ * following step of md_step sums its kinetic and potential energy, virial
+ * and list length on the device (per tile, in a fixed order, so the result
+ * is deterministic).  md_block_end stops the block and returns the means
+ * over the steps completed since md_block_begin.  md_set_state ends a block
+ * without a result; md_block_end then returns MD_ERR_STATE, as it does
+ * when no block was begun.  Both sync. */
+md_status md_block_begin(md_system *s);
+md_status md_block_end(md_system *s, md_block_t *out);
 
 /* Copy out positions, velocities and forces (each may be NULL; n x 3
  * doubles, original atom order) and the completed step count.  Sync. */

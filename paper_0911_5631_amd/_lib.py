@@ -27,6 +27,7 @@ EXPORTS = (
     "md_status_string", "md_cells_per_edge", "md_query_bytes", "md_create", "md_bin_cells",
     "md_build_nebr", "md_forces", "md_step", "md_props", "md_get_state",
     "md_get_atom_energies", "md_set_state", "md_get_cells", "md_get_bins", "md_get_pairs",
+    "md_adjust_temp", "md_block_begin", "md_block_end",
     "md_profile", "md_kernel_time", "md_destroy", "md_batch_create", "md_batch_admit",
     "md_batch_configure", "md_batch_run", "md_batch_poll", "md_batch_props", "md_batch_get_state",
     "md_batch_release", "md_batch_usage", "md_batch_destroy",
@@ -58,6 +59,12 @@ class md_props_t(C.Structure):
                 ("n_pairs", C.c_int64), ("n_rebuilds", C.c_int64), ("step", C.c_int64),
                 ("max_nebr", C.c_int32), ("max_cell", C.c_int32), ("rebuild_due", C.c_int32),
                 ("cells_per_edge", C.c_int32)]
+
+
+class md_block_t(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("ke_per_atom", C.c_double), ("pe_per_atom", C.c_double),
+                ("etot_per_atom", C.c_double), ("virial_per_atom", C.c_double),
+                ("nebr_per_atom", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -101,6 +108,12 @@ def lib():
         L.md_step.argtypes = [_P, C.c_int64]
         L.md_props.restype = st
         L.md_props.argtypes = [_P, C.POINTER(md_props_t)]
+        L.md_adjust_temp.restype = st
+        L.md_adjust_temp.argtypes = [_P, C.c_double]
+        L.md_block_begin.restype = st
+        L.md_block_begin.argtypes = [_P]
+        L.md_block_end.restype = st
+        L.md_block_end.argtypes = [_P, C.POINTER(md_block_t)]
         L.md_get_state.restype = st
         L.md_get_state.argtypes = [_P, _D, _D, _D, _I64]
         L.md_get_atom_energies.restype = st

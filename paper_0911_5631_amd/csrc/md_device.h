@@ -44,6 +44,7 @@ constexpr int NOSLOT = INT32_MIN;  // storage-index-to-slot offset of a piece no
 constexpr int NWIN = 32;           // intervals
 constexpr int WSTRIDE = 1 + 3 * NWIN;  // ints per tile: count, then (start, len, slot)
 constexpr int NPART = 8;           // doubles per tile in the property partials
+constexpr int NACC = 4;            // doubles per tile in the block accumulators
 constexpr int MAX_GRID = 2048;     // persistent-style grid bound (256 CUs x 8)
 constexpr int OVF_CAP = 4096;      // per-set overflow list of cell-layer rows
 constexpr int VSPREAD = 32;        // slots of each max-speed ring entry (one per 128-byte line)
@@ -84,6 +85,8 @@ struct SlotDev {
   int32_t *cs;                      // cell_start[ncell + 1] of the last sort
   int32_t *win;                     // per atom tile: LDS window [WSTRIDE] (count < 0: none)
   double *part;                     // per-tile partial properties [ntiles][NPART]
+  double *acc;                      // per-tile sums over the steps of a block [ntiles][NACC]:
+                                    // sum v^2, sum u_i, sum w_i, sum m_i
   unsigned long long *vring;        // max v^2 of step k: [k % 3][VSPREAD] slots, 16 words apart
   double L, halfL, invW, rn2, rc2, dt, hdt, half_shell, ushift, pad0;
   int32_t n, G, ncell, hcap, mcap, npad;
@@ -116,6 +119,8 @@ struct CtlDev {
   double ke, pe, vir, vmax2;
   int64_t sum_m;
   int32_t max_m, pad0;
+  // block sums reduced by k_props from SlotDev::acc
+  double acc_sum[NACC];
 };
 
 // Engine-wide header (device int32[8]).

@@ -79,7 +79,7 @@ md_status geometry(const md_params *p, Geometry *g) {
 
 // Layout of the per-replica state block (everything but H and W), in order.
 struct Layout {
-  size_t pv, ids, fu, cellm, cnt, tcnt, cs, win, ovf, part, vring, total;
+  size_t pv, ids, fu, cellm, cnt, tcnt, cs, win, ovf, part, acc, vring, total;
 };
 // Bytes of one set's cell counters (cnt) and tile counters (tcnt).
 size_t cnt_set_bytes(const Geometry &g) { return round_up((size_t)g.nctiles * CTILE * 4, 256); }
@@ -109,6 +109,8 @@ Layout layout(const Geometry &g) {
   b += round_up(3 * 2 * OVF_CAP * 4 + 3 * 4, 256);  // ovf[3], ovf_n[3]
   l.part = b;
   b += round_up((size_t)g.ntiles * NPART * 8, 256);
+  l.acc = b;
+  b += round_up((size_t)g.ntiles * NACC * 8, 256);
   l.vring = b;
   b += round_up((size_t)3 * VSPREAD * 16 * 8, 256);
   l.total = b;
@@ -156,6 +158,8 @@ struct Engine {
   size_t budget = 0, used = 0;
   int steps_per_run = GRAPH_CHUNK;
   int64_t host_target = 0;      // single system: target of the last md_step
+  bool accum = false;           // single system: a block is open (steps sum their properties)
+  int64_t acc_from = 0;         // single system: step at which the open block began
   int prec = 0;                 // PREC_* bits of the admitted replicas (step-kernel variants)
   // profiling of the step kernel (eager launches bracketed by events: events
   // recorded by graph nodes cannot be timed with hipEventElapsedTime)
@@ -319,6 +323,7 @@ void describe(Replica *r) {
   d.cs = (int32_t *)(b + l.cs);
   d.win = (int32_t *)(b + l.win);
   d.part = (double *)(b + l.part);
+  d.acc = (double *)(b + l.acc);
   d.vring = (unsigned long long *)(b + l.vring);
   d.W = (int32_t *)r->wmat;
   d.L = g.L;
@@ -609,7 +614,7 @@ md_status repair_cells(Engine *e, int s) {
 }
 
 hipGraphExec_t step_graph(Engine *e, int k) {
-  const int key = k * 4 + e->prec;
+  const int key = (k * 4 + e->prec) * 2 + (e->accum ? 1 : 0);
   auto it = e->graphs.find(key);
   if (it != e->graphs.end()) return it->second;
   Tables T = e->tables();
@@ -622,7 +627,7 @@ hipGraphExec_t step_graph(Engine *e, int k) {
   }
   for (int s = 0; s < k; ++s) {
     launch_sort(T, e->cgrid, s, MODE_STEP, -1, e->work);
-    launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work);
+    launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum);
   }
   launch_replay_end(T, k, e->work);
   err = hipStreamEndCapture(e->work, &g);
@@ -662,7 +667,7 @@ md_status replay(Engine *e, int k) {
     for (int s = 0; s < k; ++s) {
       launch_sort(T, e->cgrid, s, MODE_STEP, -1, e->work);
       hipError_t err = hipEventRecord(e->prof_ev[set][s][0], e->work);
-      launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work);
+      launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum);
       if (err == hipSuccess) err = hipEventRecord(e->prof_ev[set][s][1], e->work);
       if (err != hipSuccess) return e->fail("profile event record", err);
     }
@@ -1013,6 +1018,7 @@ md_status md_set_state(md_system *s, const double *pos, const double *vel) {
   CtlDev &c = e->h_ctl[0];
   const int64_t step = c.clean ? c.done : c.done + 1;
   const int variant = held_variant(c);
+  e->accum = false;  // an open block ends without a result
   if ((st = upload_state(e, r, variant, step, pos, vel)) != MD_OK) return st;
   reset_ctl(c, step, variant, c.n_rebuilds, c.max_h);
   if ((st = write_ctl(e, 0)) != MD_OK) return st;
@@ -1022,6 +1028,65 @@ md_status md_set_state(md_system *s, const double *pos, const double *vel) {
   e->host_target = step;
   if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
   return e->leave();
+}
+
+md_status md_adjust_temp(md_system *s, double temperature) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (!(temperature > 0) || !std::isfinite(temperature)) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  // the held state is clean after every md_step that met no error; the
+  // kernels skip a replica that is not (its error is reported by the next
+  // synchronising call)
+  Tables T = e->tables();
+  launch_props(T, -1, e->work);
+  launch_adjust(T, e->grid, -1, temperature, e->work);
+  if ((st = e->check("adjust launches")) != MD_OK) return st;
+  return e->leave();
+}
+
+md_status md_block_begin(md_system *s) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = sync_system(e)) != MD_OK) return st;
+  Replica *r = e->rep[0];
+  const Layout l = layout(r->g);
+  if (hipMemsetAsync((char *)r->state + l.acc, 0, l.vring - l.acc, e->work) != hipSuccess)
+    return e->fail("clear block sums");
+  e->accum = true;
+  e->acc_from = e->h_ctl[0].done;
+  return e->leave();
+}
+
+md_status md_block_end(md_system *s, md_block_t *out) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (!out) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  if ((st = e->enter()) != MD_OK) return st;
+  st = sync_system(e);
+  if (st != MD_OK && st != MD_ERR_NONFINITE && st != MD_ERR_ATOM_ESCAPED) return st;
+  Replica *r = e->rep[0];
+  const CtlDev &c = e->h_ctl[0];
+  if (!e->accum) return MD_ERR_STATE;
+  memset(out, 0, sizeof(*out));
+  const int64_t steps = c.done - e->acc_from;
+  const double n = (double)r->g.n;
+  out->steps = steps;
+  if (steps > 0) {
+    // per-atom sums over the full list count every pair twice
+    out->ke_per_atom = 0.5 * c.acc_sum[0] / (double)steps / n;
+    out->pe_per_atom = 0.5 * c.acc_sum[1] / (double)steps / n;
+    out->virial_per_atom = 0.5 * c.acc_sum[2] / (double)steps / n;
+    out->etot_per_atom = out->ke_per_atom + out->pe_per_atom;
+    out->nebr_per_atom = r->g.cell_only ? 0.0 : c.acc_sum[3] / (double)steps / n;
+  }
+  e->accum = false;
+  md_status st2 = e->leave();
+  return st != MD_OK ? st : st2;
 }
 
 md_status md_get_cells(md_system *s, int32_t *cell_of_atom) {

@@ -14,14 +14,18 @@ enum { PREC_FP32 = 1, PREC_FP64 = 2 };
 
 // One step (MODE_STEP, step index s of the replay) or an evaluation of the
 // held clean state (MODE_FORCES / MODE_BUILD).  only >= 0: that replica only.
+// accum: steps also add their properties to the block sums.
 void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int force_build,
-                 int only, int precisions, hipStream_t s);
+                 int only, int precisions, hipStream_t s, bool accum = false);
 // Advance the step counters after a replay of K steps.
 void launch_replay_end(const Tables &T, int K, hipStream_t s);
 // target = target; base = done (one replica).
 void launch_set_target(const Tables &T, int slot, long long target, hipStream_t s);
 // Reduce the property partials into the control blocks.
 void launch_props(const Tables &T, int only, hipStream_t s);
+// Step (f): scale the held clean velocities to temperature T (after
+// launch_props, which reduces the kinetic energy it scales from).
+void launch_adjust(const Tables &T, int grid, int only, double temperature, hipStream_t s);
 // Bin the held state into its cell-layer set (optionally wrapping in place).
 void launch_insert(const Tables &T, int grid, int wrap_store, int only, hipStream_t s);
 // Counting sort by cell into the other buffer variant: in a step

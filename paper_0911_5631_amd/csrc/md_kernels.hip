@@ -1037,7 +1037,9 @@ __device__ __forceinline__ void list_pair(Acc<R> &a, bool ok, uint32_t e, double
   if (ok && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
 }
 
-template <typename R>
+// ACC: the steps of a block, which sum their properties and add them to the
+// block sums.
+template <typename R, bool ACC>
 __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k, int mode, bool cells,
                           bool build, bool last) {
   const int i = lt * TILE + threadIdx.x;
@@ -1096,13 +1098,13 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
   if (act) {
     if (cells) {
       m = traverse_sorted<R>(S, i, ci, X, Y, Z, win, sx, sy, sz, xi, yi, zi, build, force,
-                             mode != MODE_STEP || last, a);
+                             mode != MODE_STEP || last || ACC, a);
       if (build) gp(S.m)[i] = m;
     } else if (list) {
       if (m <= S.mcap) {
         const double rc2 = S.rc2;
         const R ushift = (R)S.ushift;
-        const bool energy = mode != MODE_STEP || last;
+        const bool energy = mode != MODE_STEP || last || ACC;
         // entries in order, four at a time (their coordinate reads together),
         // for as long as any lane of the wave has some left: a lane past its
         // length takes the group with no effect, so the wave runs max(m)/4
@@ -1207,8 +1209,8 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
   const unsigned long long vbits = wave_max_u64((unsigned long long)__double_as_longlong(vv));
   if (l == 0) sv[w] = vbits;
   // the other properties only where somebody reads them: the last step of a
-  // run, and evaluations of a held state
-  const bool full = mode != MODE_STEP || last;
+  // run, evaluations of a held state, and the steps of a block
+  const bool full = mode != MODE_STEP || last || ACC;
   __shared__ double sh[4][8];
   if (full) {
     const int mm = act && !S.cell_only ? m : 0;
@@ -1269,12 +1271,23 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
       }
       q[6] = ((sh[0][6] + sh[1][6]) + sh[2][6]) + sh[3][6];
       q[7] = fmax(fmax(sh[0][7], sh[1][7]), fmax(sh[2][7], sh[3][7]));
+      if (ACC && mode == MODE_STEP) {
+        // this tile's part of the block sums (the tile's atoms change at a
+        // sort, the total over tiles does not)
+        auto A = gp(S.acc) + (size_t)lt * NACC;
+        A[0] = A[0] + q[0];
+        A[1] = A[1] + (q[2] + q[3]);
+        A[2] = A[2] + (q[4] + q[5]);
+        A[3] = A[3] + q[6];
+      }
     }
   }
   __syncthreads();
 }
 
-template <typename R>
+// ACC: every step of this launch also adds its properties to the block sums
+// (a separate instantiation, so steps outside a block run the plain kernel).
+template <typename R, bool ACC>
 __global__ __launch_bounds__(TILE, 4) void k_step(Tables T, int s, int mode, int force_build,
                                                int only) {
   const int nt = cview(T.hdr)[HDR_NTILES];
@@ -1319,7 +1332,7 @@ __global__ __launch_bounds__(TILE, 4) void k_step(Tables T, int s, int mode, int
     CtlDev &C = T.ctl[r];
     SlotC &S = slot(T, 2 * r + var);
     const int lt = t - S.tile_off;
-    step_tile<R>(S, C, lt, k, mode, cells, build, last);
+    step_tile<R, ACC>(S, C, lt, k, mode, cells, build, last);
     if (mode == MODE_STEP && lt == 0 && threadIdx.x == 0)
       C.var_ring[mod3(k)] = var;  // the one writer of this ring slot in this launch
     if (mode == MODE_STEP && lt == 0 && threadIdx.x < VSPREAD)
@@ -1362,40 +1375,37 @@ __global__ __launch_bounds__(TILE) void k_props(Tables T, int only) {
   if (slot(T, 2 * r).n <= 0) return;
   SlotC &S = slot_held(T, r);
   CtlDev &C = T.ctl[r];
-  __shared__ double sh[TILE][6];
-  double ke = 0, vm = 0, pe = 0, vir = 0, sm = 0, mm = 0;
+  constexpr int NV = 6 + NACC;
+  __shared__ double sh[TILE][NV];
+  double v[NV] = {};
   for (int t = threadIdx.x; t < S.ntiles; t += TILE) {
     const double *q = S.part + (size_t)t * NPART;
-    ke += q[0];
-    vm = fmax(vm, q[1]);
-    pe += q[2] + q[3];
-    vir += q[4] + q[5];
-    sm += q[6];
-    mm = fmax(mm, q[7]);
+    v[0] += q[0];
+    v[1] = fmax(v[1], q[1]);
+    v[2] += q[2] + q[3];
+    v[3] += q[4] + q[5];
+    v[4] += q[6];
+    v[5] = fmax(v[5], q[7]);
+    const double *A = S.acc + (size_t)t * NACC;
+    for (int j = 0; j < NACC; ++j) v[6 + j] += A[j];
   }
-  sh[threadIdx.x][0] = ke;
-  sh[threadIdx.x][1] = vm;
-  sh[threadIdx.x][2] = pe;
-  sh[threadIdx.x][3] = vir;
-  sh[threadIdx.x][4] = sm;
-  sh[threadIdx.x][5] = mm;
+  for (int j = 0; j < NV; ++j) sh[threadIdx.x][j] = v[j];
   __syncthreads();
   for (int h = TILE / 2; h > 0; h >>= 1) {
     if (threadIdx.x < h) {
-      sh[threadIdx.x][0] += sh[threadIdx.x + h][0];
-      sh[threadIdx.x][1] = fmax(sh[threadIdx.x][1], sh[threadIdx.x + h][1]);
-      sh[threadIdx.x][2] += sh[threadIdx.x + h][2];
-      sh[threadIdx.x][3] += sh[threadIdx.x + h][3];
-      sh[threadIdx.x][4] += sh[threadIdx.x + h][4];
-      sh[threadIdx.x][5] = fmax(sh[threadIdx.x][5], sh[threadIdx.x + h][5]);
+      for (int j = 0; j < NV; ++j) {
+        const double o = sh[threadIdx.x + h][j];
+        sh[threadIdx.x][j] = (j == 1 || j == 5) ? fmax(sh[threadIdx.x][j], o)
+                                                : sh[threadIdx.x][j] + o;
+      }
     }
     __syncthreads();
   }
   if (threadIdx.x < 3) {
-    double v = 0.0;
+    double vm = 0.0;
     for (int q = 0; q < VSPREAD; ++q)
-      v = fmax(v, __longlong_as_double((long long)S.vring[(threadIdx.x * VSPREAD + q) * 16]));
-    C.vmax_ring[threadIdx.x] = (uint64_t)__double_as_longlong(v);
+      vm = fmax(vm, __longlong_as_double((long long)S.vring[(threadIdx.x * VSPREAD + q) * 16]));
+    C.vmax_ring[threadIdx.x] = (uint64_t)__double_as_longlong(vm);
   }
   if (threadIdx.x == 0) {
     C.ke = 0.5 * sh[0][0];
@@ -1404,6 +1414,57 @@ __global__ __launch_bounds__(TILE) void k_props(Tables T, int only) {
     C.vir = 0.5 * sh[0][3];
     C.sum_m = (int64_t)sh[0][4];
     C.max_m = (int)sh[0][5];
+    for (int j = 0; j < NACC; ++j) C.acc_sum[j] = sh[0][6 + j];
+  }
+}
+
+// Step (f) during equilibration (Secs. 2.1 and 4): scale the velocities of a
+// held clean state by one factor so that sum v^2 = 3 (N - 1) T (the centre of
+// mass is at rest, leaving 3 (N - 1) degrees of freedom), from the kinetic
+// energy k_props reduced just before.  The tile's kinetic-energy and max-v^2
+// partials are recomputed from the scaled velocities, in the step kernel's
+// order; the rebuild rule keeps the maximum speed of (e), taken before (f).
+__global__ __launch_bounds__(TILE) void k_adjust(Tables T, int only, double temperature) {
+  __shared__ double sk[4];
+  __shared__ unsigned long long sv[4];
+  const int nt = cview(T.hdr)[HDR_NTILES];
+  for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
+    const int r = cview(T.tile_rep)[t];
+    if (only >= 0 && r != only) continue;
+    if (slot(T, 2 * r).n <= 0) continue;
+    SlotC &S = slot_held(T, r);
+    const CtlDev &C = T.ctl[r];
+    const double ke = C.ke;
+    if (!C.clean || C.err != 0 || S.n < 2 || !(ke > 0.0)) continue;
+    const double fac = sqrt((1.5 * (double)(S.n - 1) * temperature) / ke);
+    const int lt = t - S.tile_off;
+    const int i = lt * TILE + threadIdx.x;
+    const int vb = (int)((C.done + 1) & 1);
+    double vv = 0.0;
+    if (i < S.n) {
+      double v[3];
+      for (int a = 0; a < 3; ++a) {
+        v[a] = gp(S.V[vb][a])[i] * fac;
+        gp(S.V[vb][a])[i] = v[a];
+      }
+      vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const double ks = wave_sum(vv);
+    const unsigned long long vb2 = wave_max_u64((unsigned long long)__double_as_longlong(vv));
+    if (l == 0) {
+      sk[w] = ks;
+      sv[w] = vb2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      auto q = gp(S.part) + (size_t)lt * NPART;
+      q[0] = ((sk[0] + sk[1]) + sk[2]) + sk[3];
+      const unsigned long long b01 = sv[0] > sv[1] ? sv[0] : sv[1];
+      const unsigned long long b23 = sv[2] > sv[3] ? sv[2] : sv[3];
+      q[1] = __longlong_as_double((long long)(b01 > b23 ? b01 : b23));
+    }
+    __syncthreads();
   }
 }
 
@@ -1461,13 +1522,23 @@ void launch_sort(const Tables &T, int cgrid, int step_in_replay, int mode, int o
   hipLaunchKernelGGL(k_sort, dim3(cgrid), dim3(TILE), 0, s, T, step_in_replay, mode, only);
 }
 void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int force_build,
-                 int only, int precisions, hipStream_t s) {
-  if (precisions & PREC_FP32)
-    hipLaunchKernelGGL(k_step<float>, dim3(grid), dim3(TILE), 0, s, T, step_in_replay, mode,
-                       force_build, only);
-  if (precisions & PREC_FP64)
-    hipLaunchKernelGGL(k_step<double>, dim3(grid), dim3(TILE), 0, s, T, step_in_replay, mode,
-                       force_build, only);
+                 int only, int precisions, hipStream_t s, bool accum) {
+  if (precisions & PREC_FP32) {
+    if (accum)
+      hipLaunchKernelGGL((k_step<float, true>), dim3(grid), dim3(TILE), 0, s, T, step_in_replay,
+                         mode, force_build, only);
+    else
+      hipLaunchKernelGGL((k_step<float, false>), dim3(grid), dim3(TILE), 0, s, T, step_in_replay,
+                         mode, force_build, only);
+  }
+  if (precisions & PREC_FP64) {
+    if (accum)
+      hipLaunchKernelGGL((k_step<double, true>), dim3(grid), dim3(TILE), 0, s, T, step_in_replay,
+                         mode, force_build, only);
+    else
+      hipLaunchKernelGGL((k_step<double, false>), dim3(grid), dim3(TILE), 0, s, T, step_in_replay,
+                         mode, force_build, only);
+  }
 }
 void launch_replay_end(const Tables &T, int K, hipStream_t s) {
   hipLaunchKernelGGL(k_replay_end, dim3((T.nslots + TILE - 1) / TILE), dim3(TILE), 0, s, T, K);
@@ -1477,6 +1548,9 @@ void launch_set_target(const Tables &T, int slot, long long target, hipStream_t 
 }
 void launch_props(const Tables &T, int only, hipStream_t s) {
   hipLaunchKernelGGL(k_props, dim3(T.nslots), dim3(TILE), 0, s, T, only);
+}
+void launch_adjust(const Tables &T, int grid, int only, double temperature, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjust, dim3(grid), dim3(TILE), 0, s, T, only, temperature);
 }
 void launch_insert(const Tables &T, int grid, int wrap_store, int only, hipStream_t s) {
   hipLaunchKernelGGL(k_insert, dim3(grid), dim3(TILE), 0, s, T, wrap_store, only);

@@ -144,6 +144,17 @@ def sp_256k() -> System:
                       precision="fp32", seed=2)
 
 
+def system_s(shell: float = 0.6, seed: int = 6, n_edge: int = 48) -> System:
+    """The paper's system S (Sec. 4): simple cubic start of edge 48 (110 592
+    atoms), rho 0.8, T 1, dt 0.005, FP32 forces; shell 0.6 unless given (the
+    Table 5 runs vary it).  2000 steps: the Sec. 4 equilibration (adjustment
+    every 20 steps for 500) and the block of steps 1001-2000 of Table 4."""
+    pos, L = sc_lattice(n_edge, 0.8)
+    vel = random_velocities(len(pos), 1.0, seed)
+    return System(f"system_S_{len(pos)}_shell{shell}", pos, vel, L, 0.8, 1.0, 0.005, shell,
+                  2000, "fp32", seed)
+
+
 def sp_4m() -> System:
     """N = 4 000 000 (fcc 100^3 x 4), rho 0.8, T 1, shell 0.4, 2000 steps."""
     return fcc_system("sp_4000000_nebr_fp32", 100, 0.8, 1.0, shell=0.4, steps=2000,

@@ -134,6 +134,35 @@ class System:
         check(lib().md_props(self._h, C.byref(p)), "md_props")
         return _props_dict(p)
 
+    def adjust_temp(self, temperature: float) -> None:
+        """Step (f): scale the velocities to sum v^2 = 3 (N - 1) T (async)."""
+        check(lib().md_adjust_temp(self._h, float(temperature)), "md_adjust_temp")
+
+    def equilibrate_run(self, n_steps: int, temperature: float, equil_steps: int = 500,
+                        interval: int = 20) -> None:
+        """md_step with the equilibration of Sec. 4 folded in: after every
+        step k (absolute count) with k <= equil_steps and k a multiple of
+        interval, md_adjust_temp(temperature).  One synchronisation to read
+        the step count; the rest is enqueued."""
+        done = int(self.props()["step"])
+        end = done + int(n_steps)
+        while done < end:
+            nxt = end
+            if done < equil_steps:
+                nxt = min(end, (done // interval + 1) * interval)
+            self.step(nxt - done)
+            done = nxt
+            if done <= equil_steps and done % interval == 0:
+                self.adjust_temp(temperature)
+
+    def block_begin(self) -> None:
+        check(lib().md_block_begin(self._h), "md_block_begin")
+
+    def block_end(self) -> Dict[str, float]:
+        b = L.md_block_t()
+        check(lib().md_block_end(self._h, C.byref(b)), "md_block_end")
+        return {name: getattr(b, name) for name, _ in L.md_block_t._fields_}
+
     # -- state access (original atom order) --------------------------------
     def get_state(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray, int]:
         pos = np.empty((self.n, 3))
