@@ -172,6 +172,32 @@ def equilibrated(shell: float) -> dict:
                                         0.8: 21.64}.get(shell)}}
 
 
+def lennard_jones(rc: float, n_edge: int, steps: int) -> dict:
+    """The paper's LJ system (Sec. 4: rho 0.38, T 1.2, shell 0.8, simple cubic
+    start) with cutoff rc, no shift: 500 steps of equilibration untimed, then
+    `steps` timed steps."""
+    import torch
+    from paper_0911_5631_amd import inputs as I
+    from paper_0911_5631_amd.md import System
+    pos, L = I.sc_lattice(n_edge, 0.38)
+    vel = I.random_velocities(len(pos), 1.2, 8)
+    n = len(pos)
+    s = System(pos, vel, L, r_cut=rc, shell=0.8, even_cells=True)
+    s.equilibrate_run(500, 1.2)
+    p0 = s.props()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    pr = s.props()
+    el = time.perf_counter() - t0
+    s.close()
+    return {"r_cut": rc, "n_atoms": n, "cells": pr["cells_per_edge"] ** 3, "steps": steps,
+            "atom_steps_per_s": n * steps / el, "us_per_atom_step": el / (n * steps) * 1e6,
+            "mean_neighbours": 2.0 * pr["n_pairs"] / n,
+            "steps_per_rebuild": steps / max(pr["n_rebuilds"] - p0["n_rebuilds"], 1),
+            "pe_per_atom": pr["pe_per_atom"], "ke_per_atom": pr["ke_per_atom"]}
+
+
 def cpu_baseline(sys_in, budget_s: float):
     """The FP64 oracle on this host: same system, steps from the start until
     the time budget is used (at least 50 steps)."""
@@ -200,10 +226,11 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample (0: skip)")
     ap.add_argument("--workload", default="sp_256k",
-                    choices=["sp_256k", "sp_4m", "sp_small", "batch", "served", "equil"],
+                    choices=["sp_256k", "sp_4m", "sp_small", "batch", "served", "equil", "lj"],
                     help="single system (default sp_256k); 'batch' / 'served' run only the full "
                          "batched-replica or served-stream workload and print its JSON line; "
-                         "'equil' the paper's system S with equilibration and block averages")
+                         "'equil' the paper's system S with equilibration and block averages; "
+                         "'lj' the Lennard-Jones runs of Tables 1 and 3")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the reduced batched and served sections of the default run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -241,6 +268,19 @@ def main() -> int:
                           "higher_is_better": True, "dtype": "fp32-force/fp64-state",
                           "data": "synthetic (seeded simple cubic start)",
                           "config": {"workload": r["workload"]}, "equil": r}), flush=True)
+        return 0
+    if args.workload == "lj":
+        # Table 3: N_e = 48, r_c = 3.0 / 2.5 / 2.2; Table 1: N_e = 64, r_c = 3.0
+        runs = [lennard_jones(rc, 48, 2000) for rc in (3.0, 2.5, 2.2)]
+        runs.append(lennard_jones(3.0, 64, 2000))
+        paper_us = {(3.0, 48): 0.270, (2.5, 48): 0.176, (2.2, 48): 0.137, (3.0, 64): 0.254}
+        for r in runs:
+            r["paper_us_per_atom_step"] = paper_us[(r["r_cut"], round(r["n_atoms"] ** (1 / 3)))]
+        print(json.dumps({"metric": "atom-steps/s, Lennard-Jones rho 0.38 (r_c 3.0, N = 110 592)",
+                          "value": runs[0]["atom_steps_per_s"], "unit": "atom-steps/s",
+                          "n_gpus": 1, "higher_is_better": True, "dtype": "fp32-force/fp64-state",
+                          "data": "synthetic (seeded simple cubic start)",
+                          "config": {"workload": "lj_rc3.0_110592"}, "lj": runs}), flush=True)
         return 0
     if args.calibrate_copy > 0:
         # a plain device-to-device copy of known size whose source is no

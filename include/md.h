@@ -97,9 +97,13 @@ typedef struct {
                           the cell-list-only method (re-bin every step) */
     double dt;         /* time step */
     int32_t precision; /* md_precision */
-    int32_t nebr_cap;  /* per-atom neighbour-list capacity; 0 = 48 (atoms with
-                          longer lists are evaluated from the cells) */
-    int32_t cell_cap;  /* initial per-cell layer capacity; 0 = 16 (grown on need) */
+    int32_t nebr_cap;  /* per-atom neighbour-list capacity; 0 = from the density:
+                          max(48, 1.6 x the atoms of an r_n sphere + 16, rounded
+                          up to 16) (atoms with longer lists are evaluated from
+                          the cells) */
+    int32_t cell_cap;  /* initial per-cell layer capacity; 0 = from the density:
+                          max(16, 2 x the mean occupancy + 8, rounded up to 8)
+                          (grown on need) */
     uint32_t flags;    /* MD_EVEN_CELLS */
 } md_params;
 

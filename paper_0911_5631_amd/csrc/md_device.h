@@ -124,7 +124,7 @@ struct CtlDev {
 };
 
 // Engine-wide header (device int32[8]).
-enum { HDR_NTILES = 0, HDR_NCTILES = 1 };
+enum { HDR_NTILES = 0, HDR_NCTILES = 1, HDR_SPLIT = 2 };  // SPLIT: workgroups per cell tile in k_sort
 
 // Each replica has two descriptors (see SlotDev); CtlDev::var_ring says
 // which one holds a given state.

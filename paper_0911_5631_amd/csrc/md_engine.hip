@@ -29,8 +29,8 @@ using namespace md;
 
 namespace {
 
-constexpr int DEFAULT_MCAP = 48;
-constexpr int DEFAULT_HCAP = 16;
+constexpr int MIN_DEFAULT_MCAP = 48;
+constexpr int MIN_DEFAULT_HCAP = 16;
 constexpr int GRAPH_CHUNK = 64;      // steps per replay graph (largest)
 constexpr int PROFILE_SETS = 2;      // ping-pong event sets when profiling
 
@@ -72,8 +72,19 @@ md_status geometry(const md_params *p, Geometry *g) {
   g->nctiles = (g->ncell + 1 + CTILE - 1) / CTILE;
   g->npad = g->ntiles * TILE;
   g->cpt = (g->ncell + g->ntiles - 1) / g->ntiles;
-  g->hcap = p->cell_cap > 0 ? p->cell_cap : DEFAULT_HCAP;
-  g->mcap = g->cell_only ? 0 : (p->nebr_cap > 0 ? p->nebr_cap : DEFAULT_MCAP);
+  // default capacities from the mean density: a list holds the atoms of a
+  // sphere of radius r_n, a cell N / N_c atoms on average; the margins cover
+  // the fluctuations of a fluid (rarer excesses are handled exactly: a long
+  // list by the cell path, a full cell by the overflow list and regrowth)
+  const double rho = (double)g->n / (g->L * g->L * g->L);
+  const double sphere = 4.0 / 3.0 * M_PI * g->rn * g->rn * g->rn * rho;
+  const double occ = (double)g->n / (double)g->ncell;
+  const int mdef = (int)round_up((size_t)std::ceil(1.6 * sphere + 16.0), 16);
+  const int hdef = (int)round_up((size_t)std::ceil(2.0 * occ + 8.0), 8);
+  g->hcap = p->cell_cap > 0 ? p->cell_cap : std::max(MIN_DEFAULT_HCAP, std::min(hdef, 4096));
+  g->mcap = g->cell_only ? 0
+                         : (p->nebr_cap > 0 ? p->nebr_cap
+                                            : std::max(MIN_DEFAULT_MCAP, std::min(mdef, 4096)));
   return MD_OK;
 }
 
@@ -401,6 +412,15 @@ md_status upload_tables(Engine *e) {
   memset(hdr, 0, 32);
   hdr[HDR_NTILES] = nt;
   hdr[HDR_NCTILES] = nct;
+  // workgroups per cell tile in the sort: about 1024 atoms each (a single
+  // dense system has few cell tiles; a batch keeps one per tile)
+  int split = 1;
+  if (!e->batch && e->rep[0]) {
+    const Geometry &g = e->rep[0]->g;
+    const double occ = (double)g.n / (double)g.ncell;
+    split = std::max(1, std::min(32, (int)std::ceil(occ * CTILE / 1024.0)));
+  }
+  hdr[HDR_SPLIT] = split;
   for (int s = 0; s < e->max_slots; ++s) {
     Replica *r = e->rep[s];
     if (!r) {
@@ -424,7 +444,7 @@ md_status upload_tables(Engine *e) {
   if (err != hipSuccess) return e->fail("upload tables", err);
   if (!e->batch) {
     e->grid = std::max(1, std::min(nt, MAX_GRID));
-    e->cgrid = std::max(1, std::min(nct, MAX_GRID));
+    e->cgrid = std::max(1, std::min(nct * split, MAX_GRID));
   }
   return MD_OK;
 }

@@ -360,14 +360,21 @@ __global__ void k_kick_end(Tables T) {
 __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int only) {
   __shared__ int s_red[4];
   __shared__ int s_wsum[4];
+  __shared__ int s_bsum[4];
+  __shared__ int s_bc[TILE], s_bb[TILE], s_bp[TILE];
   const int nct = cview(T.hdr)[HDR_NCTILES];
+  // a cell tile is shared by nsp workgroups (dense systems, whose cells hold
+  // many atoms); unit u = (tile u / nsp, share u % nsp)
+  const int nsp = max(cview(T.hdr)[HDR_SPLIT], 1);
+  const int nunits = nct * nsp;
   // the decision for a replica is launch-invariant: a workgroup works it out
   // once for a run of consecutive cell tiles of one replica
   int rc = -1, var = 0;
   int64_t k = 0;
   bool skip = true, rebuild = false;
   double d1 = 0.0;
-  for (int t = xcd_block(blockIdx.x, gridDim.x); t < nct; t += gridDim.x) {
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < nunits; u += gridDim.x) {
+    const int t = u / nsp, sp = u - t * nsp;
     const int r = cview(T.ctile_rep)[t];
     CtlDev &C = T.ctl[r];
     SlotC &S0 = slot(T, 2 * r);
@@ -394,7 +401,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     }
     if (skip) continue;
     if (mode == MODE_STEP) {
-      if (t == S0.ctile_off && threadIdx.x == 0) {
+      if (t == S0.ctile_off && sp == 0 && threadIdx.x == 0) {
         // the one writer of these ring slots for step k
         C.rb_ring[mod3(k)] = rebuild ? 1 : 0;
         if (!S0.cell_only) {
@@ -422,9 +429,9 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
       for (; q + 7 * TILE < lt; q += 8 * TILE) {
         int p8[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) p8[u] = TC[q + u * TILE];
+        for (int u8 = 0; u8 < 8; ++u8) p8[u8] = TC[q + u8 * TILE];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) pre += p8[u];
+        for (int u8 = 0; u8 < 8; ++u8) pre += p8[u8];
       }
       for (; q < lt; q += TILE) pre += TC[q];
     }
@@ -445,28 +452,31 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     int before = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
     for (int q = 0; q < w; ++q) before += s_wsum[q];
     const int base = before + incl - cnt;
-    if (l == 0 && wmax > C.max_h) atomicMax(&C.max_h, wmax);
-    if (c <= S.ncell) gp(S.cs)[c] = base;  // c == ncell: the total, n
+    if (sp == 0) {
+      if (l == 0 && wmax > C.max_h) atomicMax(&C.max_h, wmax);
+      if (c <= S.ncell) gp(S.cs)[c] = base;  // c == ncell: the total, n
+    }
 
-    // scatter the cell's atoms in ascending current index
-    if (c < S.ncell && cnt > 0) {
-      const int n = S.n;
-      const double L = S.L, halfL = S.halfL;
-      auto move = [&](int a, int q) {
-        const int p = base + q;
-        if (p >= n || a < 0 || a >= n) return;  // inconsistent counts: never expected
+    // every atom goes to base of its cell + its rank by current index
+    const int n = S.n;
+    const double L = S.L, halfL = S.halfL;
+    auto move = [&](int a, int cc, int p) {
+      if (p >= n || a < 0 || a >= n) return;  // inconsistent counts: never expected
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          gp(D.P[pb][d])[p] = wrap1(gp(S.P[pb][d])[a], L, halfL);
-          gp(D.V[vb][d])[p] = gp(S.V[vb][d])[a];
-        }
-        gp(D.id)[p] = gp(S.id)[a];
-        gp(D.cell)[p] = c;
-      };
+      for (int d = 0; d < 3; ++d) {
+        gp(D.P[pb][d])[p] = wrap1(gp(S.P[pb][d])[a], L, halfL);
+        gp(D.V[vb][d])[p] = gp(S.V[vb][d])[a];
+      }
+      gp(D.id)[p] = gp(S.id)[a];
+      gp(D.cell)[p] = cc;
+    };
+    // cells of up to eight atoms (the usual ones) by the thread that holds
+    // them: a sorting network, then moves four at a time with every load of
+    // a batch issued before its stores; with shares, thread i of share i %
+    // nsp
+    const bool big = c < S.ncell && cnt > 8 && cnt <= min(S.hcap, 8191);
+    if (c < S.ncell && cnt > 0 && !big && threadIdx.x % nsp == sp) {
       if (cnt <= 8 && cnt <= S.hcap) {
-        // the usual cell: its members ordered by a sorting network, then
-        // moved four at a time with every load of a batch issued before
-        // its stores
         const int32_t *row = S.H[set] + (size_t)c * S.hcap;
         int v[8];
 #pragma unroll
@@ -478,31 +488,74 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
             double pv[4][6];
             int idv[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int a = min(max(b + u < cnt ? v[b + u] : v[0], 0), n - 1);
+            for (int u4 = 0; u4 < 4; ++u4) {
+              const int a = min(max(b + u4 < cnt ? v[b + u4] : v[0], 0), n - 1);
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                pv[u][d] = gp(S.P[pb][d])[a];
-                pv[u][3 + d] = gp(S.V[vb][d])[a];
+                pv[u4][d] = gp(S.P[pb][d])[a];
+                pv[u4][3 + d] = gp(S.V[vb][d])[a];
               }
-              idv[u] = gp(S.id)[a];
+              idv[u4] = gp(S.id)[a];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int p = base + b + u, a = v[b + u];
-              if (b + u >= cnt || p >= n || a < 0 || a >= n) continue;
+            for (int u4 = 0; u4 < 4; ++u4) {
+              const int p = base + b + u4, a = v[b + u4];
+              if (b + u4 >= cnt || p >= n || a < 0 || a >= n) continue;
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                gp(D.P[pb][d])[p] = wrap1(pv[u][d], L, halfL);
-                gp(D.V[vb][d])[p] = pv[u][3 + d];
+                gp(D.P[pb][d])[p] = wrap1(pv[u4][d], L, halfL);
+                gp(D.V[vb][d])[p] = pv[u4][3 + d];
               }
-              gp(D.id)[p] = idv[u];
+              gp(D.id)[p] = idv[u4];
               gp(D.cell)[p] = c;
             }
           }
         }
       } else {
-        visit_cell(S, set, c, cnt, move);
+        // a cell that spilled into the overflow list: repeated minimum searches
+        visit_cell(S, set, c, cnt, [&](int a, int q) { move(a, c, base + q); });
+      }
+    }
+    // larger cells whose members all sit in their rows, by the whole
+    // workgroup: their atoms are listed (big cell j holds entries
+    // s_bp[j] ... of the list), this share takes its slice, and each atom's
+    // rank is the number of smaller indices in its row
+    if (__syncthreads_or(big)) {
+      const int bv = big ? ((1 << 21) | cnt) : 0;  // (cell count, atom count)
+      int binc = bv;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(binc, o, 64);
+        if (l >= o) binc += y;
+      }
+      if (l == 63) s_bsum[w] = binc;
+      __syncthreads();
+      int bbefore = 0;
+      for (int q = 0; q < w; ++q) bbefore += s_bsum[q];
+      const int bex = bbefore + binc - bv;
+      if (big) {
+        const int j = bex >> 21;
+        s_bc[j] = c;
+        s_bb[j] = base;
+        s_bp[j] = bex & ((1 << 21) - 1);
+      }
+      const int btot = ((s_bsum[0] + s_bsum[1]) + s_bsum[2]) + s_bsum[3];
+      const int nb = btot >> 21, B = btot & ((1 << 21) - 1);
+      __syncthreads();
+      const int a0 = (int)((int64_t)B * sp / nsp), a1 = (int)((int64_t)B * (sp + 1) / nsp);
+      for (int a = a0 + (int)threadIdx.x; a < a1; a += TILE) {
+        int lo = 0, hi = nb - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_bp[mid] <= a) lo = mid;
+          else hi = mid - 1;
+        }
+        const int cj = s_bc[lo];
+        const int cntj = (lo + 1 < nb ? s_bp[lo + 1] : B) - s_bp[lo];
+        const auto row = gp((const int32_t *)S.H[set]) + (size_t)cj * S.hcap;
+        const int v = row[a - s_bp[lo]];
+        int rank = 0;
+        for (int f = 0; f < cntj; ++f) rank += row[f] < v ? 1 : 0;
+        move(v, cj, s_bb[lo] + rank);
       }
     }
     __syncthreads();

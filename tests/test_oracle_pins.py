@@ -354,3 +354,49 @@ def test_cell_only_mode_matches_list_mode_trajectory():
     d -= L * np.round(d / L)
     assert np.abs(d).max() < 1e-10 and np.abs(va - vb).max() < 1e-9
     assert np.allclose(ta[:, :3], tb[:, :3], rtol=1e-10, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Lennard-Jones with the longer cutoffs of Sec. 4 (no shift)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rc", [2.2, 2.5, 3.0])
+def test_lj_pair_set_and_forces_equal_brute_force(rc):
+    # 729 atoms at rho 0.38: L = 12.43, three cells per edge at r_n = 3.8
+    pos, L = I.sc_lattice(9, 0.38)
+    pos = I.jitter(pos, L, 0.3, seed=int(rc * 10))
+    rn = rc + 0.8
+    G = O.cells_per_edge(L, rn)
+    assert G >= 3
+    ref = O.pair_set(*O.pairs_brute(pos, L, rn)[:2])
+    pi, pj, _ = O.pairs_cells(pos, L, G, rn)
+    assert len(pi) == len(ref) and np.array_equal(O.pair_set(pi, pj), ref)
+    fb = O.forces_brute(pos, L, rc=rc, ushift=0.0)
+    scale = np.sqrt((fb.force ** 2).sum(1).mean())
+    for f in (O.forces_cells(pos, L, O.cells_per_edge(L, rc), rc=rc, ushift=0.0),
+              O.forces_pairs(pos, L, pi, pj, _, rc=rc, ushift=0.0)):
+        assert np.abs(f.force - fb.force).max() < 1e-12 * scale
+        assert abs(f.pe - fb.pe) < 1e-12 * abs(fb.pe)
+        assert f.n_inter == fb.n_inter
+
+
+@pytest.mark.parametrize("rc", [2.2, 2.5, 3.0])
+def test_lj_sc_lattice_sum_by_lattice_vectors(rc):
+    # a simple cubic crystal: every atom sees the same shells, so PE/N is half
+    # the sum of u(|n| a) over integer vectors n != 0 with |n| a < r_c (Eq. (1)
+    # without shift), counted here by enumerating the vectors directly
+    pos, L = I.sc_lattice(12, 0.38)
+    a = L / 12
+    k = int(rc / a) + 1
+    g = np.arange(-k, k + 1)
+    nx, ny, nz = np.meshgrid(g, g, g, indexing="ij")
+    r2 = (nx ** 2 + ny ** 2 + nz ** 2).ravel() * a * a
+    r2 = r2[(r2 > 0) & (r2 < rc * rc)]
+    u = 4.0 * (r2 ** -6 - r2 ** -3)
+    w = 48.0 * r2 ** -6 - 24.0 * r2 ** -3            # f(r) r^2
+    f = O.forces_cells(pos, L, O.cells_per_edge(L, rc), rc=rc, ushift=0.0)
+    n = len(pos)
+    assert abs(f.pe / n - 0.5 * u.sum()) < 1e-12 * abs(u.sum())
+    assert abs(f.virial / n - 0.5 * w.sum()) < 1e-11 * max(abs(w.sum()), 1.0)
+    assert np.abs(f.force).max() < 1e-11
+    assert f.n_inter == n * len(r2) // 2
