@@ -198,6 +198,49 @@ def lennard_jones(rc: float, n_edge: int, steps: int) -> dict:
             "pe_per_atom": pr["pe_per_atom"], "ke_per_atom": pr["ke_per_atom"]}
 
 
+def newton3_ab(reps: int) -> dict:
+    """The paper's Newton's-third-law trade on this GPU: at an evolved state
+    of the 256k soft-sphere bench system and of the LJ r_c = 3.0 system
+    (N_e = 48), build a plain storage-index list full or half and time the
+    force loop without reactions (full) and with atomic reactions (half);
+    the production step kernel's list steps are timed beside them."""
+    import torch
+    from paper_0911_5631_amd import inputs as I
+    from paper_0911_5631_amd.md import System
+    out = []
+    sp = I.sp_256k()
+    pos, L = I.sc_lattice(48, 0.38)
+    cases = [("sp_256000", sp.pos, sp.vel, sp.box, dict(shell=0.4), 200, None),
+             ("lj_rc3.0_110592", pos, I.random_velocities(len(pos), 1.2, 8), L,
+              dict(r_cut=3.0, shell=0.8, even_cells=True), 500, 1.2)]
+    for name, p, v, box, kw, warm, temp in cases:
+        s = System(p, v, box, **kw)
+        if temp:
+            s.equilibrate_run(warm, temp)
+        else:
+            s.step(warm)
+        s.props()
+        s.profile(True)
+        s.step(200)
+        s.props()
+        launches, ms = s.kernel_time()
+        s.profile(False)
+        pr = s.props()
+        full = s.newton3_ab(False, reps)
+        half = s.newton3_ab(True, reps)
+        n = len(p)
+        out.append({"system": name, "n_atoms": n, "pairs": pr["n_pairs"],
+                    "full": {"build_us": full["build_ms"] * 1e3, "force_us": full["force_ms"] * 1e3,
+                             "entries": full["n_entries"]},
+                    "half": {"build_us": half["build_ms"] * 1e3, "force_us": half["force_ms"] * 1e3,
+                             "entries": half["n_entries"]},
+                    "half_over_full_force": half["force_ms"] / full["force_ms"],
+                    "step_kernel_mean_us": ms / max(launches, 1) * 1e3})
+        s.close()
+        torch.cuda.synchronize()
+    return {"reps": reps, "cases": out}
+
+
 def cpu_baseline(sys_in, budget_s: float):
     """The FP64 oracle on this host: same system, steps from the start until
     the time budget is used (at least 50 steps)."""
@@ -226,11 +269,13 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample (0: skip)")
     ap.add_argument("--workload", default="sp_256k",
-                    choices=["sp_256k", "sp_4m", "sp_small", "batch", "served", "equil", "lj"],
+                    choices=["sp_256k", "sp_4m", "sp_small", "batch", "served", "equil", "lj",
+                             "newton3"],
                     help="single system (default sp_256k); 'batch' / 'served' run only the full "
                          "batched-replica or served-stream workload and print its JSON line; "
                          "'equil' the paper's system S with equilibration and block averages; "
-                         "'lj' the Lennard-Jones runs of Tables 1 and 3")
+                         "'lj' the Lennard-Jones runs of Tables 1 and 3; 'newton3' the full- vs "
+                         "half-list force A/B")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the reduced batched and served sections of the default run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -281,6 +326,14 @@ def main() -> int:
                           "n_gpus": 1, "higher_is_better": True, "dtype": "fp32-force/fp64-state",
                           "data": "synthetic (seeded simple cubic start)",
                           "config": {"workload": "lj_rc3.0_110592"}, "lj": runs}), flush=True)
+        return 0
+    if args.workload == "newton3":
+        r = newton3_ab(50)
+        print(json.dumps({"metric": "force-phase time, full list vs half list with atomics",
+                          "value": r["cases"][0]["half_over_full_force"], "unit": "ratio",
+                          "n_gpus": 1, "higher_is_better": False,
+                          "dtype": "fp32-force/fp64-state", "data": "synthetic",
+                          "config": {"workload": "newton3_ab"}, "newton3": r}), flush=True)
         return 0
     if args.calibrate_copy > 0:
         # a plain device-to-device copy of known size whose source is no

@@ -253,6 +253,24 @@ md_status md_get_pairs(md_system *s, int64_t cap, int32_t *i, int32_t *j, int64_
 md_status md_profile(md_system *s, int32_t enable);
 md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms);
 
+/* Newton's-third-law A/B of the force phase.  The paper drops Newton's
+ * third law on the GPU (Sec. 2.3: full lists, each atom sums its own force)
+ * where the CPU keeps each pair once and adds the reaction to the partner
+ * (Sec. 2.2).  At the held state, after a fresh sort (as md_bin_cells), this
+ * builds a plain neighbour list over the sorted cells -- storage-index
+ * entries, r^2 < r_n^2 in FP64 -- full (every j != i) or half (half != 0:
+ * j > i, each pair once), then evaluates the pair forces (FP32 on FP64
+ * separations, as the step kernel) reps times; the half form adds -f d to
+ * the partner with FP32 atomics.  Outputs (each may be NULL): force = the
+ * last evaluation's forces (n x 3, original order), build_ms / force_ms =
+ * mean event-timed durations of the build and force kernels over reps
+ * launches each, n_entries = list entries (2 x pairs full, pairs half).
+ * The list capacity is nebr_cap; MD_ERR_NEBR_OVERFLOW if a list exceeds
+ * it.  MD_ERR_STATE in cell-list-only mode.  Leaves the system as
+ * md_bin_cells does.  Sync. */
+md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
+                        double *build_ms, double *force_ms, int64_t *n_entries);
+
 /* Release the system and its device memory (synchronises its stream). */
 void md_destroy(md_system *s);
 

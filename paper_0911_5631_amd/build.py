@@ -21,7 +21,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmd_gfx950.so")
-SOURCES = ["md_kernels.hip", "md_engine.hip"]
+SOURCES = ["md_kernels.hip", "md_ab.hip", "md_engine.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

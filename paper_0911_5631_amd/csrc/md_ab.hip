@@ -1,0 +1,168 @@
+// md_ab.hip -- the Newton's-third-law A/B of the force phase.
+//
+// The paper drops Newton's third law on the GPU (Sec. 2.3): every atom keeps
+// the full list of its neighbours and sums only its own force, so no two
+// threads ever write one location.  The CPU form it gives up keeps each pair
+// once and adds the reaction to the partner (Sec. 2.2).  These kernels put
+// both forms side by side on gfx950 with one plain structure: a list over the
+// cell-sorted storage (entries are storage indices with the image code, no
+// LDS window), built full (every j != i) or half (j > i in storage order,
+// each pair once), and a force loop that either keeps its sum in registers
+// (full) or also adds -f d to the partner with FP32 atomics (half).  The
+// production step kernel is the tuned form of the full side.
+#include <hip/hip_runtime.h>
+
+#include "md_device.h"
+#include "md_kernels.h"
+
+namespace md {
+
+namespace {
+
+// Cell coordinate of one of the 27 offsets wrapped into [0, G), and the
+// image code of the atoms found there (reading 6: -L past G-1, +L below 0).
+__device__ __forceinline__ int ab_wrap(int c, int G, uint32_t *code) {
+  if (c >= G) {
+    *code = 3;
+    return c - G;
+  }
+  if (c < 0) {
+    *code = 1;
+    return c + G;
+  }
+  *code = 0;
+  return c;
+}
+
+__device__ __forceinline__ double ab_shift(uint32_t code, double L) {
+  return code == 0 ? 0.0 : (code == 1 ? L : -L);
+}
+
+// One thread per atom i (storage order): the 27 cells around i's cell,
+// offsets z-major and x fastest, each cell's atoms in storage order; keep j
+// with r^2 < r_n^2 (FP64, no FMA) and, for the half list, j > i.
+template <bool HALF>
+__global__ __launch_bounds__(TILE) void k_ab_build(const double *__restrict__ x,
+                                                  const double *__restrict__ y,
+                                                  const double *__restrict__ z,
+                                                  const int32_t *__restrict__ cell,
+                                                  const int32_t *__restrict__ cs, int n, int npad,
+                                                  int G, double L, double rn2, int mcap,
+                                                  int32_t *__restrict__ W, int32_t *__restrict__ m,
+                                                  int32_t *__restrict__ overflow) {
+  const int i = blockIdx.x * TILE + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i], zi = z[i];
+  const int c = cell[i];
+  const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+  int cnt = 0;
+  for (int oz = -1; oz <= 1; ++oz) {
+    uint32_t kz;
+    const int nz = ab_wrap(cz + oz, G, &kz);
+    const double bz = ab_shift(kz, L);
+    for (int oy = -1; oy <= 1; ++oy) {
+      uint32_t ky;
+      const int ny = ab_wrap(cy + oy, G, &ky);
+      const double by = ab_shift(ky, L);
+      for (int ox = -1; ox <= 1; ++ox) {
+        uint32_t kx;
+        const int nx = ab_wrap(cx + ox, G, &kx);
+        const double bx = ab_shift(kx, L);
+        const uint32_t code = kx | (ky << 2) | (kz << 4);
+        const int cc = (nz * G + ny) * G + nx;
+        const int lo = cs[cc], hi = cs[cc + 1];
+        for (int j = HALF ? max(lo, i + 1) : lo; j < hi; ++j) {
+          if (!HALF && j == i) continue;
+          const double dx = (xi - x[j]) + bx, dy = (yi - y[j]) + by, dz = (zi - z[j]) + bz;
+          const double s = (dx * dx + dy * dy) + dz * dz;
+          if (s < rn2) {
+            if (cnt < mcap) W[(size_t)cnt * npad + i] = (int32_t)((uint32_t)j | (code << J_BITS));
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  m[i] = min(cnt, mcap);
+  if (cnt > mcap) atomicAdd(overflow, 1);
+}
+
+// One thread per atom i: Eq. (1) (with the soft-sphere shift only in the
+// energy, not computed here) in FP32 on FP64 separations, for the entries of
+// i's list.  Full: the sum is i's force, stored once.  Half: the reaction
+// -f d goes to the partner by atomics, and i's own sum is added last (F must
+// be zero before the launch).
+template <bool HALF>
+__global__ __launch_bounds__(TILE) void k_ab_forces(const double *__restrict__ x,
+                                                   const double *__restrict__ y,
+                                                   const double *__restrict__ z,
+                                                   const int32_t *__restrict__ W,
+                                                   const int32_t *__restrict__ m, int n, int npad,
+                                                   double L, double rc2, float *__restrict__ F) {
+  const int i = blockIdx.x * TILE + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i], zi = z[i];
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  const int mi = m[i];
+  for (int q = 0; q < mi; ++q) {
+    const uint32_t e = (uint32_t)W[(size_t)q * npad + i];
+    const int j = (int)(e & IDX_MASK);
+    const double dx = (xi - x[j]) + (double)((int32_t)(e << (32 - J_BITS - 2)) >> 30) * L;
+    const double dy = (yi - y[j]) + (double)((int32_t)(e << (32 - J_BITS - 4)) >> 30) * L;
+    const double dz = (zi - z[j]) + (double)((int32_t)e >> 30) * L;
+    const double s = (dx * dx + dy * dy) + dz * dz;
+    if (s < rc2) {
+      const float sr = (float)s;
+      const float rri = __builtin_amdgcn_rcpf(sr);
+      const float rri3 = rri * rri * rri;
+      const float f = 48.f * rri3 * (rri3 - 0.5f) * rri;
+      const float ax = f * (float)dx, ay = f * (float)dy, az = f * (float)dz;
+      fx += ax;
+      fy += ay;
+      fz += az;
+      if (HALF) {
+        unsafeAtomicAdd(&F[j], -ax);
+        unsafeAtomicAdd(&F[npad + j], -ay);
+        unsafeAtomicAdd(&F[2 * (size_t)npad + j], -az);
+      }
+    }
+  }
+  if (HALF) {
+    unsafeAtomicAdd(&F[i], fx);
+    unsafeAtomicAdd(&F[npad + i], fy);
+    unsafeAtomicAdd(&F[2 * (size_t)npad + i], fz);
+  } else {
+    F[i] = fx;
+    F[npad + i] = fy;
+    F[2 * (size_t)npad + i] = fz;
+  }
+}
+
+}  // namespace
+
+void launch_ab_build(bool half, const double *x, const double *y, const double *z,
+                     const int32_t *cell, const int32_t *cs, int n, int npad, int G, double L,
+                     double rn2, int mcap, int32_t *W, int32_t *m, int32_t *overflow,
+                     hipStream_t s) {
+  const dim3 grid((n + TILE - 1) / TILE);
+  if (half)
+    hipLaunchKernelGGL(k_ab_build<true>, grid, dim3(TILE), 0, s, x, y, z, cell, cs, n, npad, G,
+                       L, rn2, mcap, W, m, overflow);
+  else
+    hipLaunchKernelGGL(k_ab_build<false>, grid, dim3(TILE), 0, s, x, y, z, cell, cs, n, npad, G,
+                       L, rn2, mcap, W, m, overflow);
+}
+
+void launch_ab_forces(bool half, const double *x, const double *y, const double *z,
+                      const int32_t *W, const int32_t *m, int n, int npad, double L, double rc2,
+                      float *F, hipStream_t s) {
+  const dim3 grid((n + TILE - 1) / TILE);
+  if (half)
+    hipLaunchKernelGGL(k_ab_forces<true>, grid, dim3(TILE), 0, s, x, y, z, W, m, n, npad, L, rc2,
+                       F);
+  else
+    hipLaunchKernelGGL(k_ab_forces<false>, grid, dim3(TILE), 0, s, x, y, z, W, m, n, npad, L,
+                       rc2, F);
+}
+
+}  // namespace md

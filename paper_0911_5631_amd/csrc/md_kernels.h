@@ -38,4 +38,15 @@ void launch_flip(const Tables &T, int only, hipStream_t s);
 // Clear the held state's cell-layer set.
 void launch_clear_set(const Tables &T, int cgrid, int only, hipStream_t s);
 
+// Newton's-third-law A/B (md_ab.hip): a plain storage-index list, full or
+// half, over the cell-sorted atoms, and its force loop (F: FP32 [3][npad];
+// zero before a half launch).
+void launch_ab_build(bool half, const double *x, const double *y, const double *z,
+                     const int32_t *cell, const int32_t *cs, int n, int npad, int G, double L,
+                     double rn2, int mcap, int32_t *W, int32_t *m, int32_t *overflow,
+                     hipStream_t s);
+void launch_ab_forces(bool half, const double *x, const double *y, const double *z,
+                      const int32_t *W, const int32_t *m, int n, int npad, double L, double rc2,
+                      float *F, hipStream_t s);
+
 }  // namespace md

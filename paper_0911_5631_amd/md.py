@@ -207,6 +207,18 @@ class System:
                                  C.byref(n)), "md_get_pairs")
         return pi[:n.value], pj[:n.value]
 
+    def newton3_ab(self, half: bool, reps: int = 1) -> Dict[str, object]:
+        """Full-list vs half-list (Newton's third law, atomics) force phase at
+        the held state: forces (original order), mean build and force kernel
+        times (ms), list entries."""
+        f = np.empty((self.n, 3))
+        b = C.c_double()
+        t = C.c_double()
+        k = C.c_int64()
+        check(lib().md_newton3_ab(self._h, 1 if half else 0, int(reps), _dptr(f), C.byref(b),
+                                  C.byref(t), C.byref(k)), "md_newton3_ab")
+        return {"force": f, "build_ms": b.value, "force_ms": t.value, "n_entries": k.value}
+
     # -- measurement ---------------------------------------------------------
     def profile(self, enable: bool) -> None:
         check(lib().md_profile(self._h, 1 if enable else 0), "md_profile")
