@@ -243,22 +243,53 @@ def newton3_ab(reps: int) -> dict:
 
 def cpu_baseline(sys_in, budget_s: float):
     """The FP64 oracle on this host: same system, steps from the start until
-    the time budget is used (at least 50 steps)."""
+    the time budget is used (at least 50 steps).  Its state after the first
+    25 steps is also set beside the GPU's after the same 25 steps, for the
+    error of each output."""
+    import numpy as np
     from oracle import oracle as O
+    from paper_0911_5631_amd.md import System
+    n = sys_in.n
     sim = O.Sim(sys_in.pos, sys_in.vel, sys_in.box, shell=sys_in.shell, dt=sys_in.dt)
     steps = 0
     t0 = time.perf_counter()
+    parity = None
     while True:
-        sim.run(25)
+        tr = sim.run(25)
         steps += 25
         el = time.perf_counter() - t0
+        if parity is None:
+            t_stop = time.perf_counter()
+            rp, rv, rf, _ = sim.state()
+            g = System(sys_in.pos, sys_in.vel, sys_in.box, shell=sys_in.shell, dt=sys_in.dt,
+                       precision=sys_in.precision)
+            g.step(25)
+            gp, gv, gf, _ = g.get_state()
+            pr = g.props()
+            g.close()
+            L = sys_in.box
+            d = gp - rp
+            d -= L * np.round(d / L)
+            scale = np.maximum(np.linalg.norm(rf, axis=1), np.sqrt((rf ** 2).sum(1).mean()))
+            parity = {
+                "step": 25,
+                "force_rel_err_max": float((np.linalg.norm(gf - rf, axis=1) / scale).max()),
+                "pe_per_atom_abs_err": abs(pr["pe"] - tr[-1, 1]) / n,
+                "virial_per_atom_abs_err": abs(pr["virial"] - tr[-1, 2]) / n,
+                "ke_per_atom_abs_err": abs(pr["ke"] - tr[-1, 0]) / n,
+                "position_abs_err_max": float(np.abs(d).max()),
+                "velocity_abs_err_max": float(np.abs(gv - rv).max()),
+                "pairs_equal": int(pr["n_pairs"]) == int(tr[-1, 4]),
+                "pe_per_atom": tr[-1, 1] / n}
+            t0 += time.perf_counter() - t_stop      # the comparison is not oracle time
+            el = time.perf_counter() - t0
         if el >= budget_s and steps >= 50:
             break
     sim.close()
-    n = sys_in.n
     return {"value": n * steps / el, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"N={n}, steps 1..{steps} from the fcc start ({el:.1f} s, one thread, "
-                      f"FP64, linked-list cells + 14-cell half list + Newton's third law)"}
+                      f"FP64, linked-list cells + 14-cell half list + Newton's third law)",
+            "parity": parity}
 
 
 def main() -> int:
