@@ -79,6 +79,32 @@ void or_pair_potential(double r, double rc, double ushift, double *u, double *fr
 }
 
 /* ------------------------------------------------------------------------ */
+/* Several species: the extension the paper names at the end of Sec. 2 (no  */
+/* parameters given there).  Each species pair (a, b) has its own epsilon,  */
+/* sigma, cutoff and energy shift: u = 4 eps ((sigma/r)^12 - (sigma/r)^6) + */
+/* shift inside the cutoff, i.e. Eq. (1) in units of sigma_ab and eps_ab.   */
+/* ------------------------------------------------------------------------ */
+#define OR_MAXSP 4
+typedef struct {
+    int32_t ns;                     /* number of species */
+    int32_t pad;
+    const int32_t *sp;              /* species of each atom, in the caller's order */
+    double eps[OR_MAXSP * OR_MAXSP], sig2[OR_MAXSP * OR_MAXSP];
+    double rc2[OR_MAXSP * OR_MAXSP], shift[OR_MAXSP * OR_MAXSP];
+} or_mix;
+
+/* f (force on i = f d) and u of pair type k at r^2 = s:
+ * f = -(1/r) du/dr = 48 eps (sigma/r)^6 ((sigma/r)^6 - 1/2) / r^2. */
+static double pair_fu_mix(const or_mix *mx, int k, double s, double *u)
+{
+    double rri = mx->sig2[k] / s;
+    double rri3 = rri * rri * rri;
+    double f = 48.0 * mx->eps[k] * rri3 * (rri3 - 0.5) / s;
+    *u = 4.0 * mx->eps[k] * rri3 * (rri3 - 1.0) + mx->shift[k];
+    return f;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Geometry (Sec. 2.1)                                                       */
 /* ------------------------------------------------------------------------ */
 
@@ -335,13 +361,20 @@ typedef struct {
     double *ua, *wa;        /* per-atom energy and virial (each pair counted on both atoms) */
     double U, W;            /* totals over pairs */
     int64_t n_inter;        /* pairs inside r_c */
+    const or_mix *mix;      /* several species, or NULL */
 } force_acc;
 
 static void acc_pair(force_acc *a, int32_t i, int32_t j, const double d[3], double s,
                      double ushift)
 {
-    double u;
-    double f = pair_fu(s, ushift, &u);
+    double u, f;
+    if (a->mix) {
+        const int k = a->mix->sp[i] * OR_MAXSP + a->mix->sp[j];
+        if (!(s < a->mix->rc2[k])) return;
+        f = pair_fu_mix(a->mix, k, s, &u);
+    } else {
+        f = pair_fu(s, ushift, &u);
+    }
     a->fx[i] += f * d[0];
     a->fy[i] += f * d[1];
     a->fz[i] += f * d[2];
@@ -369,15 +402,18 @@ static void acc_zero(force_acc *a, int64_t n)
 
 /* Pair-list force loop with Newton's third law (Sec. 2.2): for each stored
  * pair with r^2 < r_c^2, f_i += f d, f_j -= f d, U += u, W += f r^2.
+ * With mix (may be NULL) the pair's own cutoff and parameters apply (rc is
+ * then the largest cutoff).  The cell and brute-force versions below take
+ * mix in the same way.
  * ua/wa (may be NULL) receive per-atom sums with each pair counted on both
  * atoms, so sum(ua) = 2U and sum(wa) = 2W.  out[0] = U, out[1] = W,
  * out[2] = number of pairs inside r_c. */
 void or_forces_pairs(int64_t n, const double *x, const double *y, const double *z, double L,
                      int64_t np, const int32_t *pi, const int32_t *pj, const int8_t *img,
                      double rc, double ushift, double *fx, double *fy, double *fz,
-                     double *ua, double *wa, double *out)
+                     double *ua, double *wa, double *out, const or_mix *mix)
 {
-    force_acc a = {fx, fy, fz, ua, wa, 0.0, 0.0, 0};
+    force_acc a = {fx, fy, fz, ua, wa, 0.0, 0.0, 0, mix};
     acc_zero(&a, n);
     double rc2 = rc * rc;
     for (int64_t m = 0; m < np; ++m) {
@@ -411,12 +447,12 @@ static void cellforce_visit(void *vctx, int32_t i, int32_t j, const int8_t img[3
  * Sec. 2.1): same enumeration as the half list with r_n = r_c. */
 int or_forces_cells(int64_t n, const double *x, const double *y, const double *z, double L,
                     int G, double rc, double ushift, double *fx, double *fy, double *fz,
-                    double *ua, double *wa, double *out)
+                    double *ua, double *wa, double *out, const or_mix *mix)
 {
     if (G < 3) return OR_ERR_BOX_TOO_SMALL;
     cells_t cl;
     if (build_linked_cells(&cl, n, x, y, z, L, G) != OR_OK) return OR_ERR_NOMEM;
-    force_acc a = {fx, fy, fz, ua, wa, 0.0, 0.0, 0};
+    force_acc a = {fx, fy, fz, ua, wa, 0.0, 0.0, 0, mix};
     acc_zero(&a, n);
     cellforce_ctx c = {&a, rc * rc, ushift};
     half_pairs(&cl, x, y, z, L, cellforce_visit, &c);
@@ -430,9 +466,9 @@ int or_forces_cells(int64_t n, const double *x, const double *y, const double *z
 /* Brute-force forces: every i < j over all 27 images. */
 void or_forces_brute(int64_t n, const double *x, const double *y, const double *z, double L,
                      double rc, double ushift, double *fx, double *fy, double *fz,
-                     double *ua, double *wa, double *out)
+                     double *ua, double *wa, double *out, const or_mix *mix)
 {
-    force_acc a = {fx, fy, fz, ua, wa, 0.0, 0.0, 0};
+    force_acc a = {fx, fy, fz, ua, wa, 0.0, 0.0, 0, mix};
     acc_zero(&a, n);
     double rc2 = rc * rc;
     for (int64_t i = 0; i < n; ++i)
@@ -551,6 +587,7 @@ typedef struct {
     int32_t *pi, *pj;
     int8_t *img;
     double U, W;
+    const or_mix *mix;    /* several species, or NULL */
 } loop_t;
 
 static int rebuild_list(loop_t *lp)
@@ -579,11 +616,11 @@ static int compute_forces(loop_t *lp)
     double out[3];
     if (p->cell_only) {
         int rc = or_forces_cells(lp->n, lp->x, lp->y, lp->z, p->L, p->G, p->rc, p->ushift,
-                                 lp->fx, lp->fy, lp->fz, NULL, NULL, out);
+                                 lp->fx, lp->fy, lp->fz, NULL, NULL, out, lp->mix);
         if (rc != OR_OK) return rc;
     } else {
         or_forces_pairs(lp->n, lp->x, lp->y, lp->z, p->L, lp->np, lp->pi, lp->pj, lp->img,
-                        p->rc, p->ushift, lp->fx, lp->fy, lp->fz, NULL, NULL, out);
+                        p->rc, p->ushift, lp->fx, lp->fy, lp->fz, NULL, NULL, out, lp->mix);
         if (p->check_missed) {
             /* Every pair inside r_c must be in the list: count pairs inside r_c
              * by brute force; list pairs are a subset with the same r^2, so
@@ -592,7 +629,7 @@ static int compute_forces(loop_t *lp)
             if (!tx) return OR_ERR_NOMEM;
             double bo[3];
             or_forces_brute(lp->n, lp->x, lp->y, lp->z, p->L, p->rc, p->ushift, tx,
-                            tx + lp->n, tx + 2 * lp->n, NULL, NULL, bo);
+                            tx + lp->n, tx + 2 * lp->n, NULL, NULL, bo, lp->mix);
             lp->st->n_missed += (int64_t)(bo[2] - out[2]);
             free(tx);
         }
@@ -659,6 +696,8 @@ typedef struct {
     or_params p;
     or_state st;
     double *buf;  /* 9 n doubles: x y z vx vy vz fx fy fz */
+    or_mix mix;
+    int32_t *sp;  /* the mixture's own copy of the species */
 } or_sim;
 
 void or_sim_free(or_sim *s)
@@ -666,7 +705,32 @@ void or_sim_free(or_sim *s)
     if (!s) return;
     loop_free(&s->lp);
     free(s->buf);
+    free(s->sp);
     free(s);
+}
+
+/* Give the atoms species and the species pairs their parameters (a copy is
+ * kept), then evaluate the forces of the current state again (the list, built
+ * for r_n, stays).  Every cutoff must be at most the r_c of the parameters.
+ * Returns 0, or OR_ERR_ARG. */
+int or_sim_set_mix(or_sim *s, const or_mix *mx)
+{
+    const int64_t n = s->lp.n;
+    if (mx->ns < 1 || mx->ns > OR_MAXSP) return OR_ERR_ARG;
+    for (int k = 0; k < OR_MAXSP * OR_MAXSP; ++k)
+        if (mx->rc2[k] > s->p.rc * s->p.rc) return OR_ERR_ARG;
+    int32_t *sp = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!sp) return OR_ERR_NOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        if (mx->sp[i] < 0 || mx->sp[i] >= mx->ns) { free(sp); return OR_ERR_ARG; }
+        sp[i] = mx->sp[i];
+    }
+    free(s->sp);
+    s->sp = sp;
+    s->mix = *mx;
+    s->mix.sp = sp;
+    s->lp.mix = &s->mix;
+    return compute_forces(&s->lp);
 }
 
 /* Create a simulation from positions/velocities (n x 3, row-major) and run

@@ -43,6 +43,50 @@ class _Params(C.Structure):
                 ("cell_only", C.c_int32), ("check_missed", C.c_int32), ("pad", C.c_int32)]
 
 
+MAXSP = 4
+
+
+class _Mix(C.Structure):
+    _fields_ = [("ns", C.c_int32), ("pad", C.c_int32), ("sp", C.POINTER(C.c_int32)),
+                ("eps", C.c_double * 16), ("sig2", C.c_double * 16), ("rc2", C.c_double * 16),
+                ("shift", C.c_double * 16)]
+
+
+class Mixture:
+    """Species of the atoms and, per species pair (a, b), epsilon, sigma,
+    cutoff and the energy shift added inside it (n_species x n_species,
+    symmetric).  The pair energy is Eq. (1) in units of sigma_ab, eps_ab."""
+
+    def __init__(self, species, epsilon, sigma, r_cut, shift):
+        self.species = np.ascontiguousarray(species, dtype=np.int32)
+        self.epsilon = np.asarray(epsilon, dtype=np.float64)
+        self.sigma = np.asarray(sigma, dtype=np.float64)
+        self.r_cut = np.asarray(r_cut, dtype=np.float64)
+        self.shift = np.asarray(shift, dtype=np.float64)
+        self.n_species = self.epsilon.shape[0]
+
+    def struct(self) -> "_Mix":
+        m = _Mix()
+        m.ns = self.n_species
+        m.sp = self.species.ctypes.data_as(C.POINTER(C.c_int32))
+        for a in range(self.n_species):
+            for b in range(self.n_species):
+                k = a * MAXSP + b
+                m.eps[k] = self.epsilon[a, b]
+                m.sig2[k] = self.sigma[a, b] * self.sigma[a, b]
+                m.rc2[k] = self.r_cut[a, b] * self.r_cut[a, b]
+                m.shift[k] = self.shift[a, b]
+        return m
+
+    @property
+    def max_cut(self) -> float:
+        return float(self.r_cut.max())
+
+
+def _mix_arg(mix):
+    return C.byref(mix.struct()) if mix is not None else None
+
+
 class _State(C.Structure):
     _fields_ = [("disp", C.c_double), ("step", C.c_int64), ("n_rebuilds", C.c_int64),
                 ("n_missed", C.c_int64), ("rebuild", C.c_int32), ("pad", C.c_int32)]
@@ -73,13 +117,16 @@ def lib():
         L.or_pairs_brute.restype = C.c_int64
         L.or_pairs_brute.argtypes = [C.c_int64, _D, _D, _D, C.c_double, C.c_double, C.c_int64,
                                      _I32, _I32, _I8]
+        _M = C.POINTER(_Mix)
         L.or_forces_pairs.argtypes = [C.c_int64, _D, _D, _D, C.c_double, C.c_int64, _I32, _I32,
-                                      _I8, C.c_double, C.c_double, _D, _D, _D, _D, _D, _D]
+                                      _I8, C.c_double, C.c_double, _D, _D, _D, _D, _D, _D, _M]
         L.or_forces_cells.restype = C.c_int
         L.or_forces_cells.argtypes = [C.c_int64, _D, _D, _D, C.c_double, C.c_int, C.c_double,
-                                      C.c_double, _D, _D, _D, _D, _D, _D]
+                                      C.c_double, _D, _D, _D, _D, _D, _D, _M]
         L.or_forces_brute.argtypes = [C.c_int64, _D, _D, _D, C.c_double, C.c_double, C.c_double,
-                                      _D, _D, _D, _D, _D, _D]
+                                      _D, _D, _D, _D, _D, _D, _M]
+        L.or_sim_set_mix.restype = C.c_int
+        L.or_sim_set_mix.argtypes = [C.c_void_p, _M]
         L.or_force_on_atoms.argtypes = [C.c_int64, _D, _D, _D, C.c_double, C.c_double, C.c_double,
                                         C.c_int64, _I64, _D, _D, _D, _D, _D, _I32]
         L.or_neighbors_of_atom.restype = C.c_int64
@@ -210,7 +257,7 @@ def _forces_out(n):
     return [np.empty(n) for _ in range(5)], np.empty(3)
 
 
-def forces_pairs(pos, L, pi, pj, img, rc=RC_SP, ushift=1.0) -> Forces:
+def forces_pairs(pos, L, pi, pj, img, rc=RC_SP, ushift=1.0, mix=None) -> Forces:
     x, y, z = _soa(pos)
     n = len(x)
     (fx, fy, fz, ua, wa), out = _forces_out(n)
@@ -218,28 +265,30 @@ def forces_pairs(pos, L, pi, pj, img, rc=RC_SP, ushift=1.0) -> Forces:
     pj = np.ascontiguousarray(pj, dtype=np.int32)
     img = np.ascontiguousarray(img, dtype=np.int8)
     lib().or_forces_pairs(n, _p(x), _p(y), _p(z), L, len(pi), _p(pi, _I32), _p(pj, _I32),
-                          _p(img, _I8), rc, ushift, _p(fx), _p(fy), _p(fz), _p(ua), _p(wa),
-                          _p(out))
+                          _p(img, _I8), mix.max_cut if mix is not None else rc, ushift,
+                          _p(fx), _p(fy), _p(fz), _p(ua), _p(wa), _p(out), _mix_arg(mix))
     return Forces(np.stack([fx, fy, fz], axis=1), ua, wa, out[0], out[1], int(out[2]))
 
 
-def forces_cells(pos, L, G, rc=RC_SP, ushift=1.0) -> Forces:
+def forces_cells(pos, L, G, rc=RC_SP, ushift=1.0, mix=None) -> Forces:
     x, y, z = _soa(pos)
     n = len(x)
     (fx, fy, fz, ua, wa), out = _forces_out(n)
-    rcode = lib().or_forces_cells(n, _p(x), _p(y), _p(z), L, G, rc, ushift, _p(fx), _p(fy),
-                                  _p(fz), _p(ua), _p(wa), _p(out))
+    rcode = lib().or_forces_cells(n, _p(x), _p(y), _p(z), L, G,
+                                  mix.max_cut if mix is not None else rc, ushift, _p(fx),
+                                  _p(fy), _p(fz), _p(ua), _p(wa), _p(out), _mix_arg(mix))
     if rcode != 0:
         raise ValueError("oracle forces_cells failed: %d" % rcode)
     return Forces(np.stack([fx, fy, fz], axis=1), ua, wa, out[0], out[1], int(out[2]))
 
 
-def forces_brute(pos, L, rc=RC_SP, ushift=1.0) -> Forces:
+def forces_brute(pos, L, rc=RC_SP, ushift=1.0, mix=None) -> Forces:
     x, y, z = _soa(pos)
     n = len(x)
     (fx, fy, fz, ua, wa), out = _forces_out(n)
-    lib().or_forces_brute(n, _p(x), _p(y), _p(z), L, rc, ushift, _p(fx), _p(fy), _p(fz),
-                          _p(ua), _p(wa), _p(out))
+    lib().or_forces_brute(n, _p(x), _p(y), _p(z), L, mix.max_cut if mix is not None else rc,
+                          ushift, _p(fx), _p(fy), _p(fz), _p(ua), _p(wa), _p(out),
+                          _mix_arg(mix))
     return Forces(np.stack([fx, fy, fz], axis=1), ua, wa, out[0], out[1], int(out[2]))
 
 
@@ -322,6 +371,14 @@ class Sim:
             if m <= cap:
                 return pi[:m].copy(), pj[:m].copy(), img[:m].copy()
             cap = int(m)
+
+    def set_species(self, mix: "Mixture") -> None:
+        """Several species (the pair cutoffs at most this Sim's rc); the
+        forces of the current state are evaluated again."""
+        self._mix = mix
+        rc = lib().or_sim_set_mix(self._h, C.byref(mix.struct()))
+        if rc != 0:
+            raise ValueError("oracle set_species failed: %d" % rc)
 
     def adjust_temp(self, temperature: float) -> float:
         """Step (f): scale the velocities to sum v^2 = 3 (N - 1) T; returns
