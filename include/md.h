@@ -193,6 +193,23 @@ md_status md_step(md_system *s, int64_t n_steps);
  * Sync; returns latched device errors. */
 md_status md_props(md_system *s, md_props_t *out);
 
+/* Several species, the extension the paper names at the end of Sec. 2
+ * (with no parameters there): species[i] in [0, n_species) for every atom
+ * (original order), and per species pair (a, b) -- row-major n_species x
+ * n_species arrays, symmetric -- epsilon >= 0, sigma > 0, the cutoff
+ * (0 < r_cut[a][b] <= the system's r_cut, whose r_c + shell sizes the cells
+ * and lists) and the energy added inside it.  A pair then interacts through
+ * Eq. (1) in units of sigma_ab and epsilon_ab: u = 4 eps ((sigma/r)^12 -
+ * (sigma/r)^6) + shift for r < r_cut.  With one species of sigma = epsilon
+ * = 1 this is the plain potential with the same arithmetic.  At most 4
+ * species.  The held state is sorted and evaluated again (as md_bin_cells);
+ * md_set_state keeps the species of the original indices.  Single systems
+ * only.  MD_ERR_INVALID_ARG for an out-of-range species or parameter or an
+ * asymmetric table.  Sync. */
+md_status md_set_species(md_system *s, int32_t n_species, const int32_t *species,
+                         const double *epsilon, const double *sigma, const double *r_cut,
+                         const double *shift);
+
 /* Step (f) of the loop (Sec. 2.1), used during the equilibration period of
  * Sec. 4 (every 20 steps for the first 500): scale every velocity of the
  * held state by one factor so that sum v^2 = 3 (N - 1) T, T = temperature
@@ -266,8 +283,8 @@ md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms);
  * mean event-timed durations of the build and force kernels over reps
  * launches each, n_entries = list entries (2 x pairs full, pairs half).
  * The list capacity is nebr_cap; MD_ERR_NEBR_OVERFLOW if a list exceeds
- * it.  MD_ERR_STATE in cell-list-only mode.  Leaves the system as
- * md_bin_cells does.  Sync. */
+ * it.  MD_ERR_STATE in cell-list-only mode and for mixtures.  Leaves the
+ * system as md_bin_cells does.  Sync. */
 md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
                         double *build_ms, double *force_ms, int64_t *n_entries);
 

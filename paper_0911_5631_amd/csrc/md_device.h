@@ -48,6 +48,18 @@ constexpr int NACC = 4;            // doubles per tile in the block accumulators
 constexpr int MAX_GRID = 2048;     // persistent-style grid bound (256 CUs x 8)
 constexpr int OVF_CAP = 4096;      // per-set overflow list of cell-layer rows
 constexpr int VSPREAD = 32;        // slots of each max-speed ring entry (one per 128-byte line)
+constexpr int MAXSP = 4;           // species of a mixture
+
+// Pair parameters of a mixture, for species pair k = a * MAXSP + b: Eq. (1)
+// in units of sigma_ab and epsilon_ab, r^2 < rc2 inside the pair's cutoff,
+// energy shift added there.  Stored as products the force loop uses.
+struct PairTab {
+  double rc2[MAXSP * MAXSP];
+  double sig2[MAXSP * MAXSP];   // sigma^2
+  double eps48[MAXSP * MAXSP];  // 48 epsilon
+  double eps4[MAXSP * MAXSP];   // 4 epsilon
+  double shift[MAXSP * MAXSP];
+};
 
 // Latched error bits (CtlDev::err).
 enum : int32_t {
@@ -88,13 +100,16 @@ struct SlotDev {
   double *acc;                      // per-tile sums over the steps of a block [ntiles][NACC]:
                                     // sum v^2, sum u_i, sum w_i, sum m_i
   unsigned long long *vring;        // max v^2 of step k: [k % 3][VSPREAD] slots, 16 words apart
+  int32_t *sp, *sp_alt;             // mixture: species of each storage position (else null)
+  const PairTab *tab;               // mixture: pair parameters (else null)
   double L, halfL, invW, rn2, rc2, dt, hdt, half_shell, ushift, pad0;
   int32_t n, G, ncell, hcap, mcap, npad;
   int32_t ntiles;    // atom tiles: ceil(n / TILE)
   int32_t nctiles;   // cell tiles: ceil((ncell + 1) / CTILE), so one holds cell_start[ncell]
   int32_t tile_off, ctile_off;
   int32_t cpt;       // cells cleared per atom tile: ceil(ncell / ntiles)
-  int32_t fp64, cell_only, pad1;
+  int32_t fp64, cell_only;
+  int32_t nsp;       // species of a mixture (0: one species, the r_c / ushift above)
 };
 
 // Per-replica mutable control block.  Written by the host between launches,

@@ -141,6 +141,11 @@ struct Replica {
   SlotDev dev[2]{};   // descriptor variants
   void *state = nullptr, *hmat = nullptr, *wmat = nullptr;
   size_t bytes = 0;
+  // a mixture: species buffers (two variants) and pair table on the device,
+  // the species in original order on the host
+  void *mixbuf = nullptr;
+  int nsp = 0;
+  std::vector<int32_t> species;
 };
 
 }  // namespace
@@ -171,6 +176,7 @@ struct Engine {
   int64_t host_target = 0;      // single system: target of the last md_step
   bool accum = false;           // single system: a block is open (steps sum their properties)
   int64_t acc_from = 0;         // single system: step at which the open block began
+  bool mix = false;             // single system: several species (the mixture kernels)
   int prec = 0;                 // PREC_* bits of the admitted replicas (step-kernel variants)
   // profiling of the step kernel (eager launches bracketed by events: events
   // recorded by graph nodes cannot be timed with hipEventElapsedTime)
@@ -357,6 +363,12 @@ void describe(Replica *r) {
   d.cpt = g.cpt;
   d.fp64 = g.fp64 ? 1 : 0;
   d.cell_only = g.cell_only ? 1 : 0;
+  if (r->mixbuf) {
+    d.tab = (const PairTab *)r->mixbuf;
+    d.sp = (int32_t *)((char *)r->mixbuf + round_up(sizeof(PairTab), 256));
+    d.sp_alt = d.sp + np;
+    d.nsp = r->nsp;
+  }
   SlotDev e = d;
   for (int a = 0; a < 3; ++a) {
     std::swap(e.P[0][a], e.P[1][a]);
@@ -364,6 +376,7 @@ void describe(Replica *r) {
   }
   std::swap(e.id, e.id_alt);
   std::swap(e.cell, e.cell_alt);
+  std::swap(e.sp, e.sp_alt);
   const int32_t to = r->dev[0].tile_off, co = r->dev[0].ctile_off;
   r->dev[0] = d;
   r->dev[1] = e;
@@ -499,7 +512,7 @@ md_status evaluate_clean(Engine *e, int only, int mode, int force_build) {
   Tables T = e->tables();
   md_status st = host_sort(e, only);
   if (st != MD_OK) return st;
-  launch_step(T, e->grid, 0, mode, force_build, only, e->prec, e->work);
+  launch_step(T, e->grid, 0, mode, force_build, only, e->prec, e->work, false, e->mix);
   launch_props(T, only, e->work);
   if ((st = e->check("evaluate launches")) != MD_OK) return st;
   if ((st = read_ctl(e)) != MD_OK) return st;
@@ -550,6 +563,7 @@ void free_replica(Engine *e, Replica *r) {
   e->dfree(r->state);
   e->dfree(r->hmat);
   e->dfree(r->wmat);
+  e->dfree(r->mixbuf);
   delete r;
 }
 
@@ -634,7 +648,7 @@ md_status repair_cells(Engine *e, int s) {
 }
 
 hipGraphExec_t step_graph(Engine *e, int k) {
-  const int key = (k * 4 + e->prec) * 2 + (e->accum ? 1 : 0);
+  const int key = ((k * 4 + e->prec) * 2 + (e->accum ? 1 : 0)) * 2 + (e->mix ? 1 : 0);
   auto it = e->graphs.find(key);
   if (it != e->graphs.end()) return it->second;
   Tables T = e->tables();
@@ -647,7 +661,7 @@ hipGraphExec_t step_graph(Engine *e, int k) {
   }
   for (int s = 0; s < k; ++s) {
     launch_sort(T, e->cgrid, s, MODE_STEP, -1, e->work);
-    launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum);
+    launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum, e->mix);
   }
   launch_replay_end(T, k, e->work);
   err = hipStreamEndCapture(e->work, &g);
@@ -687,7 +701,7 @@ md_status replay(Engine *e, int k) {
     for (int s = 0; s < k; ++s) {
       launch_sort(T, e->cgrid, s, MODE_STEP, -1, e->work);
       hipError_t err = hipEventRecord(e->prof_ev[set][s][0], e->work);
-      launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum);
+      launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum, e->mix);
       if (err == hipSuccess) err = hipEventRecord(e->prof_ev[set][s][1], e->work);
       if (err != hipSuccess) return e->fail("profile event record", err);
     }
@@ -850,6 +864,24 @@ md_status set_force_step(Engine *e, int s) {
   return write_ctl(e, s);
 }
 
+// Upload the species (original order) into the storage order of descriptor
+// variant v, whose id array maps storage positions to original indices.
+md_status upload_species(Engine *e, Replica *r, int v) {
+  const int64_t n = r->g.n;
+  std::vector<int32_t> id(n), sp(n);
+  hipError_t err = hipMemcpyAsync(id.data(), r->dev[v].id, (size_t)n * 4, hipMemcpyDeviceToHost,
+                                  e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("species ids", err);
+  for (int64_t p = 0; p < n; ++p) {
+    const int32_t i = id[p];
+    sp[p] = (i >= 0 && i < n) ? r->species[i] : 0;
+  }
+  err = hipMemcpyAsync(r->dev[v].sp, sp.data(), (size_t)n * 4, hipMemcpyHostToDevice, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  return err == hipSuccess ? MD_OK : e->fail("upload species", err);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -969,7 +1001,7 @@ md_status md_forces(md_system *s) {
   Engine *e = s->e;
   if ((st = e->enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
-  launch_step(e->tables(), e->grid, 0, MODE_FORCES, 0, -1, e->prec, e->work);
+  launch_step(e->tables(), e->grid, 0, MODE_FORCES, 0, -1, e->prec, e->work, false, e->mix);
   if ((st = sync_system(e)) != MD_OK) return st;
   return e->leave();
 }
@@ -1040,6 +1072,7 @@ md_status md_set_state(md_system *s, const double *pos, const double *vel) {
   const int variant = held_variant(c);
   e->accum = false;  // an open block ends without a result
   if ((st = upload_state(e, r, variant, step, pos, vel)) != MD_OK) return st;
+  if (r->mixbuf && (st = upload_species(e, r, variant)) != MD_OK) return st;
   reset_ctl(c, step, variant, c.n_rebuilds, c.max_h);
   if ((st = write_ctl(e, 0)) != MD_OK) return st;
   if (clear_sets(e, r) != hipSuccess) return e->fail("clear sets");
@@ -1109,6 +1142,60 @@ md_status md_block_end(md_system *s, md_block_t *out) {
   return st != MD_OK ? st : st2;
 }
 
+md_status md_set_species(md_system *s, int32_t n_species, const int32_t *species,
+                         const double *epsilon, const double *sigma, const double *r_cut,
+                         const double *shift) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (!species || !epsilon || !sigma || !r_cut || !shift) return MD_ERR_INVALID_ARG;
+  if (n_species < 1 || n_species > MAXSP) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  Replica *r = e->rep[0];
+  const int ns = n_species;
+  const int64_t n = r->g.n;
+  PairTab t{};
+  for (int a = 0; a < ns; ++a)
+    for (int b = 0; b < ns; ++b) {
+      const int q = a * ns + b, qt = b * ns + a, k = a * MAXSP + b;
+      if (epsilon[q] != epsilon[qt] || sigma[q] != sigma[qt] || r_cut[q] != r_cut[qt] ||
+          shift[q] != shift[qt])
+        return MD_ERR_INVALID_ARG;
+      if (!(sigma[q] > 0) || !std::isfinite(sigma[q]) || !(epsilon[q] >= 0) ||
+          !std::isfinite(epsilon[q]) || !(r_cut[q] > 0) || r_cut[q] > r->g.rc ||
+          !std::isfinite(shift[q]))
+        return MD_ERR_INVALID_ARG;
+      t.rc2[k] = r_cut[q] * r_cut[q];
+      t.sig2[k] = sigma[q] * sigma[q];
+      t.eps48[k] = 48.0 * epsilon[q];
+      t.eps4[k] = 4.0 * epsilon[q];
+      t.shift[k] = shift[q];
+    }
+  for (int64_t i = 0; i < n; ++i)
+    if (species[i] < 0 || species[i] >= ns) return MD_ERR_INVALID_ARG;
+  if ((st = e->enter()) != MD_OK) return st;
+  if ((st = require_clean(e)) != MD_OK) return st;
+  if (!r->mixbuf) {
+    const size_t bytes = round_up(sizeof(PairTab), 256) + (size_t)2 * r->g.npad * 4;
+    r->mixbuf = e->dmalloc(bytes);
+    if (!r->mixbuf) return MD_ERR_OOM;
+    r->bytes += bytes;
+    e->used += bytes;
+  }
+  r->nsp = ns;
+  r->species.assign(species, species + n);
+  describe(r);
+  hipError_t err = hipMemcpyAsync(r->mixbuf, &t, sizeof(PairTab), hipMemcpyHostToDevice, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("pair table", err);
+  if ((st = upload_species(e, r, held_variant(e->h_ctl[0]))) != MD_OK) return st;
+  if ((st = upload_tables(e)) != MD_OK) return st;
+  e->mix = true;
+  // the held state with its new forces (sorted again, as md_bin_cells)
+  if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
+  if ((st = set_force_step(e, 0)) != MD_OK) return st;
+  return e->leave();
+}
+
 md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
                         double *build_ms, double *force_ms, int64_t *n_entries) {
   md_status st = sys_ok(s);
@@ -1116,7 +1203,7 @@ md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
   if (reps < 1 || reps > 100000) return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
   Replica *r = e->rep[0];
-  if (r->g.cell_only) return MD_ERR_STATE;
+  if (r->g.cell_only || r->nsp > 0) return MD_ERR_STATE;
   if ((st = e->enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
   // a fresh sort of the held state (as md_bin_cells), so the cells hold the

@@ -14,9 +14,10 @@ enum { PREC_FP32 = 1, PREC_FP64 = 2 };
 
 // One step (MODE_STEP, step index s of the replay) or an evaluation of the
 // held clean state (MODE_FORCES / MODE_BUILD).  only >= 0: that replica only.
-// accum: steps also add their properties to the block sums.
+// accum: steps also add their properties to the block sums; mix: the
+// replicas have several species.
 void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int force_build,
-                 int only, int precisions, hipStream_t s, bool accum = false);
+                 int only, int precisions, hipStream_t s, bool accum = false, bool mix = false);
 // Advance the step counters after a replay of K steps.
 void launch_replay_end(const Tables &T, int K, hipStream_t s);
 // target = target; base = done (one replica).

@@ -47,6 +47,7 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gp(T *p) {
   return (__attribute__((address_space(1))) T *)p;
 }
 typedef const __attribute__((address_space(1))) double *gcdouble;
+typedef const __attribute__((address_space(1))) int32_t *gcint;
 
 // Replica descriptors are written by the host only, between launches: read
 // through the constant address space their fields are scalar loads held in
@@ -460,6 +461,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     // every atom goes to base of its cell + its rank by current index
     const int n = S.n;
     const double L = S.L, halfL = S.halfL;
+    const bool mixsp = S.nsp > 0;  // a mixture: the species move with the atoms
     auto move = [&](int a, int cc, int p) {
       if (p >= n || a < 0 || a >= n) return;  // inconsistent counts: never expected
 #pragma unroll
@@ -469,6 +471,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
       }
       gp(D.id)[p] = gp(S.id)[a];
       gp(D.cell)[p] = cc;
+      if (mixsp) gp(D.sp)[p] = gp(S.sp)[a];
     };
     // cells of up to eight atoms (the usual ones) by the thread that holds
     // them: a sorting network, then moves four at a time with every load of
@@ -486,7 +489,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
         for (int b = 0; b < 8; b += 4) {
           if (b < cnt) {
             double pv[4][6];
-            int idv[4];
+            int idv[4], spv[4];
 #pragma unroll
             for (int u4 = 0; u4 < 4; ++u4) {
               const int a = min(max(b + u4 < cnt ? v[b + u4] : v[0], 0), n - 1);
@@ -496,6 +499,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
                 pv[u4][3 + d] = gp(S.V[vb][d])[a];
               }
               idv[u4] = gp(S.id)[a];
+              spv[u4] = mixsp ? gp(S.sp)[a] : 0;
             }
 #pragma unroll
             for (int u4 = 0; u4 < 4; ++u4) {
@@ -508,6 +512,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
               }
               gp(D.id)[p] = idv[u4];
               gp(D.cell)[p] = c;
+              if (mixsp) gp(D.sp)[p] = spv[u4];
             }
           }
         }
@@ -604,6 +609,26 @@ __device__ __forceinline__ void pair_accum(Acc<R> &a, double dx, double dy, doub
   a.fz += f * (R)dz;
   if (energy) {
     a.u += (R)4 * rri3 * (rri3 - (R)1) + ushift;
+    a.w += f * sr;
+  }
+}
+
+// The same for species pair k of a mixture: Eq. (1) in units of sigma_ab and
+// epsilon_ab, r^-2 scaled by sigma^2 (with sigma = epsilon = 1 every product
+// is the one-species arithmetic above).
+template <typename R>
+__device__ __forceinline__ void pair_accum_mix(Acc<R> &a, double dx, double dy, double dz,
+                                               double s, const PairTab *t, int k, bool energy) {
+  const R sr = (R)s;
+  const R rinv = recip(sr);
+  const R rri = (R)t->sig2[k] * rinv;
+  const R rri3 = rri * rri * rri;
+  const R f = (R)t->eps48[k] * rri3 * (rri3 - (R)0.5) * rinv;
+  a.fx += f * (R)dx;
+  a.fy += f * (R)dy;
+  a.fz += f * (R)dz;
+  if (energy) {
+    a.u += (R)t->eps4[k] * rri3 * (rri3 - (R)1) + (R)t->shift[k];
     a.w += f * sr;
   }
 }
@@ -855,8 +880,11 @@ __device__ void make_window(SlotC &S, int lt, Window &w, int *scratch) {
 }
 
 // Stage the window's atoms (positions of the current step) into LDS.
+// MIX: the species of the window's atoms go to ssp beside the coordinates.
+template <bool MIX>
 __device__ __forceinline__ void stage_window(const int *wt, gcdouble X, gcdouble Y, gcdouble Z,
-                                             double *sx, double *sy, double *sz) {
+                                             double *sx, double *sy, double *sz, gcint SP,
+                                             int8_t *ssp) {
   // the intervals fill slots 0 .. total-1 in order: thread t takes slots
   // t, t + TILE, ... (at most SPT of them) and walks the interval table
   // forward.  The source indices are found first; the loads then go out in
@@ -883,12 +911,14 @@ __device__ __forceinline__ void stage_window(const int *wt, gcdouble X, gcdouble
   auto batch = [&](auto first, auto count) {
     constexpr int U0 = decltype(first)::value, NU = decltype(count)::value;
     double bx[NU], by[NU], bz[NU];
+    int bs[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int j = max(src[U0 + u], 0);  // a slot beyond the window reads atom 0, unstored
       bx[u] = X[j];
       by[u] = Y[j];
       bz[u] = Z[j];
+      if (MIX) bs[u] = SP[j];
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -897,6 +927,7 @@ __device__ __forceinline__ void stage_window(const int *wt, gcdouble X, gcdouble
         sx[sl] = bx[u];
         sy[sl] = by[u];
         sz[sl] = bz[u];
+        if (MIX) ssp[sl] = (int8_t)bs[u];
       }
     }
   };
@@ -913,13 +944,16 @@ __device__ __forceinline__ void stage_window(const int *wt, gcdouble X, gcdouble
 // into W when building (window slot, or storage index with GFLAG), and
 // accumulates the forces of pairs with r^2 < r_c^2.  Positions were wrapped
 // by the sort, so they are read as stored.
-template <typename R>
+// MIX: a mixture; the candidates' species come from ssp (LDS) or SP, atom
+// i's is spi, and each pair takes its own cutoff and parameters from tab.
+template <typename R, bool MIX>
 __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble X,
                                                gcdouble Y, gcdouble Z, const Window &w,
                                                const double *sx, const double *sy,
                                                const double *sz, double xi, double yi,
                                                double zi, bool build, bool force, bool energy,
-                                               Acc<R> &a) {
+                                               Acc<R> &a, const int8_t *ssp, gcint SP, int spi,
+                                               const PairTab *tab) {
   const int G = S.G;
   const double L = S.L, rn2 = S.rn2, rc2 = S.rc2;
   const R ushift = (R)S.ushift;
@@ -941,6 +975,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
     const bool lds = ALL_LDS || delta != NOSLOT;
     for (int j0 = lo; j0 < hi; j0 += 4) {
       double xj[4], yj[4], zj[4];
+      int sj[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = min(j0 + u, hi - 1);
@@ -948,10 +983,12 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
           xj[u] = sx[j + delta];
           yj[u] = sy[j + delta];
           zj[u] = sz[j + delta];
+          if (MIX) sj[u] = ssp[j + delta];
         } else {
           xj[u] = X[j];
           yj[u] = Y[j];
           zj[u] = Z[j];
+          if (MIX) sj[u] = SP[j];
         }
       }
 #pragma unroll
@@ -971,7 +1008,12 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
             if (m < mcap) Wc[(size_t)m * np] = (int32_t)(idx | code);
             ++m;
           }
-          if (force && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
+          if (MIX) {
+            const int kk = (spi * MAXSP + sj[u]) & (MAXSP * MAXSP - 1);
+            if (force && s < tab->rc2[kk]) pair_accum_mix<R>(a, dx, dy, dz, s, tab, kk, energy);
+          } else if (force && s < rc2) {
+            pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
+          }
         }
       }
     }
@@ -1030,9 +1072,10 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
 // 27-cell traversal over the cell-layer rows of set `set` (positions of the
 // current step, unsorted since the last rebuild).  Used for an atom whose
 // neighbour list overflowed its capacity at the last build: forces only.
-template <typename R>
+template <typename R, bool MIX>
 __device__ void traverse_rows(SlotC &S, int set, int i, int ci, gcdouble X, gcdouble Y,
-                              gcdouble Z, double xi, double yi, double zi, Acc<R> &a) {
+                              gcdouble Z, double xi, double yi, double zi, Acc<R> &a, gcint SP,
+                              int spi, const PairTab *tab) {
   const int G = S.G;
   const double L = S.L, halfL = S.halfL, rc2 = S.rc2;
   const R ushift = (R)S.ushift;
@@ -1050,35 +1093,47 @@ __device__ void traverse_rows(SlotC &S, int set, int i, int ci, gcdouble X, gcdo
       const double dy = (yi - wrap1(Y[j], L, halfL)) + by;
       const double dz = (zi - wrap1(Z[j], L, halfL)) + bz;
       const double s = (dx * dx + dy * dy) + dz * dz;
-      if (s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, true);
+      if (MIX) {
+        const int kk = (spi * MAXSP + SP[j]) & (MAXSP * MAXSP - 1);
+        if (s < tab->rc2[kk]) pair_accum_mix<R>(a, dx, dy, dz, s, tab, kk, true);
+      } else if (s < rc2) {
+        pair_accum<R>(a, dx, dy, dz, s, ushift, true);
+      }
     });
   }
 }
 
 // Coordinates of neighbour-list entry e: from the LDS window, or from
 // global memory when the entry carries a storage index.
+template <bool MIX>
 __device__ __forceinline__ void entry_pos(uint32_t e, gcdouble X, gcdouble Y, gcdouble Z,
                                           const double *sx, const double *sy, const double *sz,
-                                          double &xj, double &yj, double &zj) {
+                                          double &xj, double &yj, double &zj, gcint SP,
+                                          const int8_t *ssp, int &sj) {
   const uint32_t idx = e & IDX_MASK;
   if (e & GFLAG) {
     xj = X[idx];
     yj = Y[idx];
     zj = Z[idx];
+    if (MIX) sj = SP[idx];
   } else {
     xj = sx[idx];
     yj = sy[idx];
     zj = sz[idx];
+    if (MIX) sj = ssp[idx];
   }
 }
 
 // One neighbour-list entry e (index + image code) of atom i, counted when ok.
 // SHIFT = false when no entry of the wave's current group carries an image
 // code.
-template <typename R, bool SHIFT>
+// MIX: kk = the species pair (masked into the table: a masked-off entry may
+// carry any species byte).
+template <typename R, bool SHIFT, bool MIX>
 __device__ __forceinline__ void list_pair(Acc<R> &a, bool ok, uint32_t e, double xi, double yi,
                                           double zi, double xj, double yj, double zj, double L,
-                                          double rc2, R ushift, bool energy) {
+                                          double rc2, R ushift, bool energy, int kk,
+                                          const PairTab *tab) {
   double dx = xi - xj, dy = yi - yj, dz = zi - zj;
   if (SHIFT) {
     // each 2-bit field sign-extended is the multiple of L (exact products)
@@ -1087,12 +1142,17 @@ __device__ __forceinline__ void list_pair(Acc<R> &a, bool ok, uint32_t e, double
     dz = dz + (double)((int32_t)e >> 30) * L;
   }
   const double s = (dx * dx + dy * dy) + dz * dz;
-  if (ok && s < rc2) pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
+  if (MIX) {
+    if (ok && s < tab->rc2[kk]) pair_accum_mix<R>(a, dx, dy, dz, s, tab, kk, energy);
+  } else if (ok && s < rc2) {
+    pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
+  }
 }
 
 // ACC: the steps of a block, which sum their properties and add them to the
-// block sums.
-template <typename R, bool ACC>
+// block sums.  MIX: a mixture (species staged with the window, pair
+// parameters in LDS).
+template <typename R, bool ACC, bool MIX>
 __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k, int mode, bool cells,
                           bool build, bool last) {
   const int i = lt * TILE + threadIdx.x;
@@ -1136,6 +1196,22 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
   // the tile's LDS window: made with the list at a sort, read back otherwise
   __shared__ double sx[WCAP], sy[WCAP], sz[WCAP];
   __shared__ Window win;
+  // a mixture: the window's species and the pair table (the barriers below
+  // publish them)
+  __shared__ typename std::conditional<MIX, PairTab, char>::type stab;
+  __shared__ int8_t ssp_store[MIX ? WCAP : 1];
+  const PairTab *tab = nullptr;
+  int8_t *ssp = nullptr;
+  const gcint SP = gp((const int32_t *)S.sp);
+  int spi = 0;
+  if constexpr (MIX) {
+    tab = &stab;
+    ssp = ssp_store;
+    constexpr int NT = (int)(sizeof(PairTab) / sizeof(double));
+    if (threadIdx.x < NT)
+      ((double *)&stab)[threadIdx.x] = gp((const double *)S.tab)[threadIdx.x];
+    if (act) spi = SP[i];
+  }
   if (cells) {
     make_window(S, lt, win, (int *)sx);
   } else if (list) {
@@ -1143,15 +1219,15 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
     __syncthreads();
   }
   if (cells || list) {
-    stage_window(win.wt, X, Y, Z, sx, sy, sz);
+    stage_window<MIX>(win.wt, X, Y, Z, sx, sy, sz, SP, ssp);
     __syncthreads();
   }
 
   Acc<R> a{(R)0, (R)0, (R)0, (R)0, (R)0};
   if (act) {
     if (cells) {
-      m = traverse_sorted<R>(S, i, ci, X, Y, Z, win, sx, sy, sz, xi, yi, zi, build, force,
-                             mode != MODE_STEP || last || ACC, a);
+      m = traverse_sorted<R, MIX>(S, i, ci, X, Y, Z, win, sx, sy, sz, xi, yi, zi, build, force,
+                                  mode != MODE_STEP || last || ACC, a, ssp, SP, spi, tab);
       if (build) gp(S.m)[i] = m;
     } else if (list) {
       if (m <= S.mcap) {
@@ -1169,6 +1245,7 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
                                   ok[3] ? e3 : 0u};
           const uint32_t any = (eg[0] | eg[1]) | (eg[2] | eg[3]);
           double xj[4], yj[4], zj[4];
+          int sj[4] = {0, 0, 0, 0};
           if (__ballot((any & GFLAG) != 0) == 0) {
             // the usual case: every entry of the wave is a window slot
 #pragma unroll
@@ -1177,22 +1254,23 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
               xj[u] = sx[sl];
               yj[u] = sy[sl];
               zj[u] = sz[sl];
+              if (MIX) sj[u] = ssp[sl];
             }
           } else {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              entry_pos(eg[u], X, Y, Z, sx, sy, sz, xj[u], yj[u], zj[u]);
+              entry_pos<MIX>(eg[u], X, Y, Z, sx, sy, sz, xj[u], yj[u], zj[u], SP, ssp, sj[u]);
           }
           if (__ballot((any >> J_BITS) != 0) == 0) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              list_pair<R, false>(a, ok[u], eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2,
-                                  ushift, energy);
+              list_pair<R, false, MIX>(a, ok[u], eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2,
+                                       ushift, energy, (spi * MAXSP + sj[u]) & (MAXSP * MAXSP - 1), tab);
           } else {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              list_pair<R, true>(a, ok[u], eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2,
-                                 ushift, energy);
+              list_pair<R, true, MIX>(a, ok[u], eg[u], xi, yi, zi, xj[u], yj[u], zj[u], L, rc2,
+                                      ushift, energy, (spi * MAXSP + sj[u]) & (MAXSP * MAXSP - 1), tab);
           }
         };
 #pragma unroll
@@ -1208,8 +1286,8 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
       } else {
         // the list overflowed its capacity at the last build: evaluate this
         // atom from the cell-layer rows of the current positions (exact)
-        traverse_rows<R>(S, set, i, gp(S.cell)[i], X, Y, Z, wrap1(xi, L, halfL),
-                         wrap1(yi, L, halfL), wrap1(zi, L, halfL), a);
+        traverse_rows<R, MIX>(S, set, i, gp(S.cell)[i], X, Y, Z, wrap1(xi, L, halfL),
+                              wrap1(yi, L, halfL), wrap1(zi, L, halfL), a, SP, spi, tab);
       }
     }
   }
@@ -1340,9 +1418,10 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
 
 // ACC: every step of this launch also adds its properties to the block sums
 // (a separate instantiation, so steps outside a block run the plain kernel).
-template <typename R, bool ACC>
-__global__ __launch_bounds__(TILE, 4) void k_step(Tables T, int s, int mode, int force_build,
-                                               int only) {
+// MIX: the replicas are mixtures (more LDS: three workgroups per CU).
+template <typename R, bool ACC, bool MIX>
+__global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int mode,
+                                                          int force_build, int only) {
   const int nt = cview(T.hdr)[HDR_NTILES];
   // what a workgroup decides per replica is launch-invariant: it is worked
   // out once for a run of consecutive tiles of one replica (every tile, for
@@ -1385,7 +1464,7 @@ __global__ __launch_bounds__(TILE, 4) void k_step(Tables T, int s, int mode, int
     CtlDev &C = T.ctl[r];
     SlotC &S = slot(T, 2 * r + var);
     const int lt = t - S.tile_off;
-    step_tile<R, ACC>(S, C, lt, k, mode, cells, build, last);
+    step_tile<R, ACC, MIX>(S, C, lt, k, mode, cells, build, last);
     if (mode == MODE_STEP && lt == 0 && threadIdx.x == 0)
       C.var_ring[mod3(k)] = var;  // the one writer of this ring slot in this launch
     if (mode == MODE_STEP && lt == 0 && threadIdx.x < VSPREAD)
@@ -1574,24 +1653,29 @@ void launch_sort(const Tables &T, int cgrid, int step_in_replay, int mode, int o
                  hipStream_t s) {
   hipLaunchKernelGGL(k_sort, dim3(cgrid), dim3(TILE), 0, s, T, step_in_replay, mode, only);
 }
+template <typename R, bool ACC, bool MIX>
+static void launch_k_step(const Tables &T, int grid, int step_in_replay, int mode,
+                          int force_build, int only, hipStream_t s) {
+  hipLaunchKernelGGL((k_step<R, ACC, MIX>), dim3(grid), dim3(TILE), 0, s, T, step_in_replay, mode,
+                     force_build, only);
+}
+template <typename R>
+static void launch_k_step_r(const Tables &T, int grid, int step_in_replay, int mode,
+                            int force_build, int only, hipStream_t s, bool accum, bool mix) {
+  if (accum) {
+    if (mix) launch_k_step<R, true, true>(T, grid, step_in_replay, mode, force_build, only, s);
+    else launch_k_step<R, true, false>(T, grid, step_in_replay, mode, force_build, only, s);
+  } else {
+    if (mix) launch_k_step<R, false, true>(T, grid, step_in_replay, mode, force_build, only, s);
+    else launch_k_step<R, false, false>(T, grid, step_in_replay, mode, force_build, only, s);
+  }
+}
 void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int force_build,
-                 int only, int precisions, hipStream_t s, bool accum) {
-  if (precisions & PREC_FP32) {
-    if (accum)
-      hipLaunchKernelGGL((k_step<float, true>), dim3(grid), dim3(TILE), 0, s, T, step_in_replay,
-                         mode, force_build, only);
-    else
-      hipLaunchKernelGGL((k_step<float, false>), dim3(grid), dim3(TILE), 0, s, T, step_in_replay,
-                         mode, force_build, only);
-  }
-  if (precisions & PREC_FP64) {
-    if (accum)
-      hipLaunchKernelGGL((k_step<double, true>), dim3(grid), dim3(TILE), 0, s, T, step_in_replay,
-                         mode, force_build, only);
-    else
-      hipLaunchKernelGGL((k_step<double, false>), dim3(grid), dim3(TILE), 0, s, T, step_in_replay,
-                         mode, force_build, only);
-  }
+                 int only, int precisions, hipStream_t s, bool accum, bool mix) {
+  if (precisions & PREC_FP32)
+    launch_k_step_r<float>(T, grid, step_in_replay, mode, force_build, only, s, accum, mix);
+  if (precisions & PREC_FP64)
+    launch_k_step_r<double>(T, grid, step_in_replay, mode, force_build, only, s, accum, mix);
 }
 void launch_replay_end(const Tables &T, int K, hipStream_t s) {
   hipLaunchKernelGGL(k_replay_end, dim3((T.nslots + TILE - 1) / TILE), dim3(TILE), 0, s, T, K);

@@ -134,6 +134,19 @@ class System:
         check(lib().md_props(self._h, C.byref(p)), "md_props")
         return _props_dict(p)
 
+    def set_species(self, species, epsilon, sigma, r_cut, shift) -> None:
+        """Several species: per-atom species (original order) and per species
+        pair epsilon, sigma, cutoff and energy shift (n x n, symmetric)."""
+        species = np.ascontiguousarray(species, dtype=np.int32)
+        if species.shape != (self.n,):
+            raise ValueError("species must have one entry per atom")
+        tabs = [np.ascontiguousarray(t, dtype=np.float64) for t in (epsilon, sigma, r_cut, shift)]
+        ns = tabs[0].shape[0]
+        if any(t.shape != (ns, ns) for t in tabs):
+            raise ValueError("pair tables must be n_species x n_species")
+        check(lib().md_set_species(self._h, ns, species.ctypes.data_as(_I32),
+                                   *[_dptr(t) for t in tabs]), "md_set_species")
+
     def adjust_temp(self, temperature: float) -> None:
         """Step (f): scale the velocities to sum v^2 = 3 (N - 1) T (async)."""
         check(lib().md_adjust_temp(self._h, float(temperature)), "md_adjust_temp")
