@@ -241,6 +241,39 @@ def newton3_ab(reps: int) -> dict:
     return {"reps": reps, "cases": out}
 
 
+def mixture(steps: int) -> dict:
+    """A soft-sphere binary mixture of the bench size (inputs.mixture_256k)
+    against the same start with one species: the cost of the per-pair
+    parameters (species staged with the window, a table lookup per pair)."""
+    import torch
+    from paper_0911_5631_amd import inputs as I
+    from paper_0911_5631_amd.md import System
+    wl, species = I.mixture_256k()
+    eps, sig, rc, sh = I.binary_wca()
+    out = {}
+    for name in ("mixture", "one_species"):
+        s = System(wl.pos, wl.vel, wl.box, r_cut=float(rc.max()) if name == "mixture" else
+                   I.RC_SOFT_SPHERE, shell=wl.shell, dt=wl.dt)
+        if name == "mixture":
+            s.set_species(species, eps, sig, rc, sh)
+        s.step(200)
+        p0 = s.props()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        pr = s.props()
+        el = time.perf_counter() - t0
+        s.close()
+        out[name] = {"atom_steps_per_s": wl.n * steps / el,
+                     "mean_neighbours": 2.0 * pr["n_pairs"] / wl.n,
+                     "steps_per_rebuild": steps / max(pr["n_rebuilds"] - p0["n_rebuilds"], 1),
+                     "pe_per_atom": pr["pe_per_atom"]}
+    out["ratio"] = out["mixture"]["atom_steps_per_s"] / out["one_species"]["atom_steps_per_s"]
+    out.update({"n_atoms": wl.n, "steps": steps, "species_b_fraction": 0.5,
+                "sigma": sig.tolist(), "epsilon": eps.tolist()})
+    return out
+
+
 def cpu_baseline(sys_in, budget_s: float):
     """The FP64 oracle on this host: same system, steps from the start until
     the time budget is used (at least 50 steps).  Its state after the first
@@ -301,12 +334,12 @@ def main() -> int:
                     help="time budget of the CPU-oracle sample (0: skip)")
     ap.add_argument("--workload", default="sp_256k",
                     choices=["sp_256k", "sp_4m", "sp_small", "batch", "served", "equil", "lj",
-                             "newton3"],
+                             "newton3", "mixture"],
                     help="single system (default sp_256k); 'batch' / 'served' run only the full "
                          "batched-replica or served-stream workload and print its JSON line; "
                          "'equil' the paper's system S with equilibration and block averages; "
                          "'lj' the Lennard-Jones runs of Tables 1 and 3; 'newton3' the full- vs "
-                         "half-list force A/B")
+                         "half-list force A/B; 'mixture' a binary soft-sphere mixture")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the reduced batched and served sections of the default run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -357,6 +390,14 @@ def main() -> int:
                           "n_gpus": 1, "higher_is_better": True, "dtype": "fp32-force/fp64-state",
                           "data": "synthetic (seeded simple cubic start)",
                           "config": {"workload": "lj_rc3.0_110592"}, "lj": runs}), flush=True)
+        return 0
+    if args.workload == "mixture":
+        r = mixture(4000)
+        print(json.dumps({"metric": "atom-steps/s, binary soft-sphere mixture (N = 256 000)",
+                          "value": r["mixture"]["atom_steps_per_s"], "unit": "atom-steps/s",
+                          "n_gpus": 1, "higher_is_better": True,
+                          "dtype": "fp32-force/fp64-state", "data": "synthetic",
+                          "config": {"workload": "binary_wca_256000"}, "mixture": r}), flush=True)
         return 0
     if args.workload == "newton3":
         r = newton3_ab(50)

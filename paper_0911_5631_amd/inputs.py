@@ -155,6 +155,28 @@ def system_s(shell: float = 0.6, seed: int = 6, n_edge: int = 48) -> System:
                   2000, "fp32", seed)
 
 
+def binary_wca(sig_aa: float = 1.0, sig_bb: float = 1.2, eps_ab: float = 1.5):
+    """Pair tables of a soft-sphere (WCA) binary mixture: sigma_ab the mean of
+    the two diameters, epsilon 1 for like pairs and eps_ab for unlike ones,
+    cutoff 2^(1/6) sigma_ab and shift epsilon_ab (so u(r_c) = 0).  Returns
+    (epsilon, sigma, r_cut, shift), each 2 x 2."""
+    sab = 0.5 * (sig_aa + sig_bb)
+    sig = np.array([[sig_aa, sab], [sab, sig_bb]])
+    eps = np.array([[1.0, eps_ab], [eps_ab, 1.0]])
+    return eps, sig, RC_SOFT_SPHERE * sig, eps.copy()
+
+
+def mixture_256k(seed: int = 9):
+    """N = 256 000 (fcc 40^3 x 4) at rho 0.75, T 1, shell 0.4: half the atoms
+    (seeded random choice) of species B, the binary_wca() tables.  Returns
+    (System, species)."""
+    sys_ = fcc_system("binary_wca_256000", 40, 0.75, 1.0, shell=0.4, steps=2000,
+                      precision="fp32", seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    species = (rng.permutation(sys_.n) < sys_.n // 2).astype(np.int32)
+    return sys_, species
+
+
 def sp_4m() -> System:
     """N = 4 000 000 (fcc 100^3 x 4), rho 0.8, T 1, shell 0.4, 2000 steps."""
     return fcc_system("sp_4000000_nebr_fp32", 100, 0.8, 1.0, shell=0.4, steps=2000,
