@@ -274,6 +274,40 @@ def mixture(steps: int) -> dict:
     return out
 
 
+def _oracle_replica(args):
+    """One replica stepped by the oracle in 25-step chunks for budget_s."""
+    pos, vel, box, shell, dt, budget_s = args
+    from oracle import oracle as O
+    sim = O.Sim(pos, vel, box, shell=shell, dt=dt)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        sim.run(25)
+        steps += 25
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    sim.close()
+    return len(pos) * steps, el
+
+
+def cpu_baseline_replicas(systems, budget_s: float) -> dict:
+    """The oracle on the replica workload: independent replicas, one per host
+    core (the oracle is single-threaded), each stepping for budget_s; the
+    aggregate is the sum of their rates.  Runs before the GPU is touched."""
+    from concurrent.futures import ProcessPoolExecutor
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    sample = systems[:cores]
+    jobs = [(s.pos, s.vel, s.box, s.shell, s.dt, budget_s) for s in sample]
+    with ProcessPoolExecutor(cores) as ex:
+        res = list(ex.map(_oracle_replica, jobs))
+    rate = sum(a / el for a, el in res)
+    return {"value": rate, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"replicas 1..{cores} of the batch (N {min(s.n for s in sample)}.."
+                      f"{max(s.n for s in sample)}), one oracle process per core, "
+                      f"{budget_s:.0f} s each from their starts"}
+
+
 def cpu_baseline(sys_in, budget_s: float):
     """The FP64 oracle on this host: same system, steps from the start until
     the time budget is used (at least 50 steps).  Its state after the first
@@ -351,6 +385,14 @@ def main() -> int:
               "(multi-GPU sharding is not implemented); run with --gpus 1", file=sys.stderr)
         return 2
 
+    cpu_rep = None
+    if args.workload == "batch" and args.cpu_seconds > 0:
+        from paper_0911_5631_amd import inputs as I
+        cpu_rep = cpu_baseline_replicas(I.replica_batch(n_replicas=256, steps=5000),
+                                        args.cpu_seconds)
+        print(f"# oracle on the replicas: {cpu_rep['value']:.4g} atom-steps/s on "
+              f"{cpu_rep['cores']} cores", file=sys.stderr, flush=True)
+
     import torch
     from paper_0911_5631_amd import inputs as I
     from paper_0911_5631_amd.md import System
@@ -358,10 +400,12 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.workload == "batch":
         r = batched(256, 5000, 32, 1000)
-        print(json.dumps({"metric": "atom-steps/s, 256 batched replicas", "value": r["atom_steps_per_s"],
-                          "unit": "atom-steps/s", "n_gpus": 1, "higher_is_better": True,
-                          "data": "synthetic", "config": {"workload": "replica_batch_256"},
-                          "batched": r}), flush=True)
+        line = {"metric": "atom-steps/s, 256 batched replicas", "value": r["atom_steps_per_s"],
+                "unit": "atom-steps/s", "n_gpus": 1, "higher_is_better": True,
+                "data": "synthetic", "config": {"workload": "replica_batch_256"}, "batched": r}
+        if cpu_rep:
+            line["cpu_baseline"] = cpu_rep
+        print(json.dumps(line), flush=True)
         return 0
     if args.workload == "served":
         r = served(256, 50.0, 50, 1000, 20000, 32.0)
