@@ -1,6 +1,6 @@
 """Parity of the gfx950 path (through the C ABI) with the FP64 CPU oracle.
 
-Bars (stated in the benchmark spec and derived where it is silent):
+Bars (the stated tolerances of the GPU path, derived where none is stated):
   * cell assignment, storage order and neighbour-pair sets: bit-exact;
   * FP32 forces: max_i |dF_i| / max(|F_i|, F_rms) <= 1e-5 (a per-component
     relative error is undefined where F_i ~ 0, so the scale is the larger of
