@@ -178,3 +178,30 @@ def test_lj_table1_system_counts():
     n_u = 3000 / pr["n_rebuilds"]
     assert 13.0 <= n_u <= 17.0, n_u
     assert abs(blk["ke_per_atom"] - 1.5 * 1.2) < 0.05
+
+
+def test_lj_batch_equals_solo_bit_for_bit():
+    """A batch sorts each cell tile with one workgroup, a single dense system
+    shares it among several: the storage order (ranks by index) and so every
+    trajectory are the same either way."""
+    from paper_0911_5631_amd.md import Batch, System
+    specs = [lj_fluid(13, 21, amp=0.1), lj_fluid(15, 22, amp=0.1)]
+    b = Batch(1 << 31, 4, 16)
+    slots = [b.admit(p, v, L, 120, r_cut=2.5, shell=SHELL) for p, v, L in specs]
+    out = {}
+    for _ in range(50):
+        if len(out) == len(specs):
+            break
+        b.run()
+        for slot in b.poll():
+            out[slot] = b.get_state(slot)
+            b.release(slot)
+    b.close()
+    for slot, (p, v, L) in zip(slots, specs):
+        s = System(p, v, L, r_cut=2.5, shell=SHELL)
+        s.step(120)
+        sp, sv, _, step = s.get_state()
+        s.close()
+        gp, gv, gstep = out[slot]
+        assert gstep == step == 120
+        assert np.array_equal(gp, sp) and np.array_equal(gv, sv)
