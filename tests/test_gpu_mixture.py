@@ -177,3 +177,27 @@ def test_species_follow_atoms_through_sorts_and_set_state():
     with pytest.raises(MDError):
         s.set_species(sp, eps, sig, rc * 1.5, sh)  # beyond the system's cutoff
     s.close()
+
+
+def test_mixture_block_means_match_oracle():
+    """Block averages of a mixture (the accumulating mixture kernel) against
+    the oracle's trace over the same steps, FP64."""
+    pos, vel, L, sp = binary_fluid(11, 7, amp=0.08)
+    eps, sig, rc, sh = wca_binary()
+    n = len(pos)
+    s = _system(pos, vel, L, r_cut=rc.max(), shell=0.4, precision="fp64")
+    s.set_species(sp, eps, sig, rc, sh)
+    ref = O.Sim(pos, vel, L, shell=0.4, rc=rc.max(), ushift=0.0)
+    ref.set_species(O.Mixture(sp, eps, sig, rc, sh))
+    s.step(20)
+    ref.run(20)
+    s.block_begin()
+    s.step(60)
+    blk = s.block_end()
+    want = O.block_means(ref.run(60), n, 1, 60)
+    s.close()
+    ref.close()
+    assert blk["steps"] == 60
+    for key in ("ke_per_atom", "pe_per_atom", "virial_per_atom"):
+        assert abs(blk[key] - want[key]) <= 1e-10 * max(abs(want[key]), 1.0), key
+    assert abs(blk["nebr_per_atom"] - want["nebr_per_atom"]) <= 1e-12 * want["nebr_per_atom"]
