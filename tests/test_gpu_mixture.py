@@ -201,3 +201,26 @@ def test_mixture_block_means_match_oracle():
     for key in ("ke_per_atom", "pe_per_atom", "virial_per_atom"):
         assert abs(blk[key] - want[key]) <= 1e-10 * max(abs(want[key]), 1.0), key
     assert abs(blk["nebr_per_atom"] - want["nebr_per_atom"]) <= 1e-12 * want["nebr_per_atom"]
+
+
+def test_mixture_energy_conservation_10k_steps():
+    """The WCA mixture's pair energies are continuous at every cutoff (each
+    shift is eps_ab), so the FP32-force trajectory conserves energy as the
+    one-species one does: drift of the mean total energy per atom between
+    the first and last 1 000 steps below 2e-4 over 10^4 steps."""
+    pos, L = I.fcc_lattice(9, 0.75)
+    vel = I.random_velocities(len(pos), 1.0, 13)
+    sp = (np.random.Generator(np.random.PCG64(14)).random(len(pos)) < 0.5).astype(np.int32)
+    eps, sig, rc, sh = wca_binary()
+    n = len(pos)
+    s = _system(pos, vel, L, r_cut=rc.max(), shell=0.4)
+    s.set_species(sp, eps, sig, rc, sh)
+    e = []
+    for _ in range(100):
+        s.step(100)
+        pr = s.props()
+        e.append((pr["ke"] + pr["pe"]) / n)
+    e = np.array(e)
+    assert abs(e[-10:].mean() - e[:10].mean()) / abs(e[:10].mean()) < 2e-4
+    assert s.props()["step"] == 10000 and s.props()["n_rebuilds"] > 300
+    s.close()
