@@ -95,6 +95,30 @@ def test_full_size_sampled_parity(make, steps, n_sample):
     s.close()
 
 
+def test_lj_full_size_sampled_parity():
+    """Lennard-Jones at Table 1's largest size (N_e = 64, 262 144 atoms,
+    r_c = 3.0, shell 0.8, rho 0.38): sampled forces and energies against the
+    oracle's brute-force per-atom sums after steps with rebuilds, and sampled
+    neighbour rows of a list built at those positions, bit-exact."""
+    pos0, L = I.sc_lattice(64, 0.38)
+    vel0 = I.random_velocities(len(pos0), 1.2, 17)
+    n = len(pos0)
+    s = _system(pos0, vel0, L, r_cut=3.0, shell=0.8, even_cells=True)
+    s.step(40)
+    assert s.props()["n_rebuilds"] >= 1
+    pos, vel, force, _ = s.get_state()
+    idx = np.sort(np.random.Generator(np.random.PCG64(18)).choice(n, 64, replace=False))
+    f_ref, u_ref, _, _ = O.force_on_atoms(pos, L, idx.astype(np.int64), rc=3.0, ushift=0.0)
+    scale = np.maximum(np.linalg.norm(f_ref, axis=1), math.sqrt((f_ref ** 2).sum(1).mean()))
+    assert float((np.linalg.norm(force[idx] - f_ref, axis=1) / scale).max()) <= FORCE_TOL
+    u_atom, _ = s.atom_energies()
+    assert float(np.abs(u_atom[idx] - u_ref).max()) <= 1e-5 * max(1.0, float(np.abs(u_ref).max()))
+    s.bin_cells()
+    pos2, _, _, _ = s.get_state()
+    _check_sampled_neighbours(s, pos2, L, 3.8, idx[:24])
+    s.close()
+
+
 def test_single_atom_and_pair():
     # one atom: no pairs, no force, nothing to do but drift
     L = 5.0
