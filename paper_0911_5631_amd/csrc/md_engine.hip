@@ -864,6 +864,114 @@ md_status set_force_step(Engine *e, int s) {
   return write_ctl(e, s);
 }
 
+// Device scratch of one md_newton3_ab call, released however the call ends.
+struct AbScratch {
+  Engine *e;
+  int32_t *W = nullptr, *M = nullptr;  // list [mcap][npad]; lengths [npad] + overflow count
+  float *F = nullptr;                  // forces [3][npad]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  explicit AbScratch(Engine *eng) : e(eng) {}
+  ~AbScratch() {
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
+    (void)hipStreamSynchronize(e->work);
+    e->dfree(W);
+    e->dfree(M);
+    e->dfree(F);
+  }
+};
+
+// Mean event-timed duration (ms) of `reps` launches of `launch` (with `before`
+// enqueued ahead of each, untimed).
+template <class Before, class Launch>
+hipError_t time_launches(Engine *e, hipEvent_t (&ev)[2], int reps, Before &&before,
+                         Launch &&launch, double *mean_ms) {
+  double total = 0.0;
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < reps && err == hipSuccess; ++k) {
+    float ms = 0.f;
+    err = before();
+    if (err == hipSuccess) err = hipEventRecord(ev[0], e->work);
+    if (err == hipSuccess) {
+      launch();
+      err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipEventRecord(ev[1], e->work);
+    if (err == hipSuccess) err = hipEventSynchronize(ev[1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    total += ms;
+  }
+  *mean_ms = total / reps;
+  return err;
+}
+
+md_status newton3_ab(Engine *e, Replica *r, bool half, int reps, double *force,
+                     double *build_ms, double *force_ms, int64_t *n_entries) {
+  // a fresh sort of the held state (as md_bin_cells), so the cells hold the
+  // current positions
+  md_status st = evaluate_clean(e, -1, MODE_FORCES, 1);
+  if (st == MD_OK) st = set_force_step(e, 0);
+  if (st != MD_OK) return st;
+  const Geometry &g = r->g;
+  const CtlDev &c = e->h_ctl[0];
+  const SlotDev &d = r->dev[held_variant(c)];
+  const int pb = (int)(c.done & 1);
+  const int n = (int)g.n, np = g.npad, mcap = g.mcap;
+  AbScratch x(e);
+  x.W = (int32_t *)e->dmalloc((size_t)mcap * np * 4);
+  x.M = (int32_t *)e->dmalloc((size_t)np * 4 + 256);
+  x.F = (float *)e->dmalloc((size_t)3 * np * 4);
+  if (!x.W || !x.M || !x.F) return MD_ERR_OOM;
+  int32_t *dovf = x.M + np;
+  hipError_t err = hipEventCreate(&x.ev[0]);
+  if (err == hipSuccess) err = hipEventCreate(&x.ev[1]);
+  if (err == hipSuccess) err = hipMemsetAsync(dovf, 0, 4, e->work);
+  double tb = 0.0, tf = 0.0;
+  if (err == hipSuccess)
+    err = time_launches(
+        e, x.ev, reps, [] { return hipSuccess; },
+        [&] {
+          launch_ab_build(half, d.P[pb][0], d.P[pb][1], d.P[pb][2], d.cell, d.cs, n, np, g.G,
+                          g.L, g.rn * g.rn, mcap, x.W, x.M, dovf, e->work);
+        },
+        &tb);
+  int32_t ovf = 0;
+  if (err == hipSuccess) err = hipMemcpyAsync(&ovf, dovf, 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("newton3 a/b build", err);
+  if (ovf != 0) return MD_ERR_NEBR_OVERFLOW;
+  // the half form accumulates into F: zero it before every launch
+  err = time_launches(
+      e, x.ev, reps,
+      [&] { return half ? hipMemsetAsync(x.F, 0, (size_t)3 * np * 4, e->work) : hipSuccess; },
+      [&] {
+        launch_ab_forces(half, d.P[pb][0], d.P[pb][1], d.P[pb][2], x.W, x.M, n, np, g.L,
+                         g.rc * g.rc, x.F, e->work);
+      },
+      &tf);
+  std::vector<float> hf((size_t)3 * np);
+  std::vector<int32_t> hid(n), hm(n);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(hf.data(), x.F, (size_t)3 * np * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(hid.data(), d.id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(hm.data(), x.M, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("newton3 a/b forces", err);
+  int64_t tot = 0;
+  for (int p = 0; p < n; ++p) {
+    tot += hm[p];
+    const int i = hid[p];
+    if (force && i >= 0 && i < n)
+      for (int a = 0; a < 3; ++a) force[3 * (size_t)i + a] = hf[(size_t)a * np + p];
+  }
+  if (n_entries) *n_entries = tot;
+  if (build_ms) *build_ms = tb;
+  if (force_ms) *force_ms = tf;
+  return MD_OK;
+}
+
 // Upload the species (original order) into the storage order of descriptor
 // variant v, whose id array maps storage positions to original indices.
 md_status upload_species(Engine *e, Replica *r, int v) {
@@ -1206,97 +1314,7 @@ md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
   if (r->g.cell_only || r->nsp > 0) return MD_ERR_STATE;
   if ((st = e->enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
-  // a fresh sort of the held state (as md_bin_cells), so the cells hold the
-  // current positions
-  if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
-  if ((st = set_force_step(e, 0)) != MD_OK) return st;
-  const Geometry &g = r->g;
-  const CtlDev &c = e->h_ctl[0];
-  const SlotDev &d = r->dev[held_variant(c)];
-  const int pb = (int)(c.done & 1);
-  const int n = (int)g.n, np = g.npad, mcap = g.mcap;
-  int32_t *W = (int32_t *)e->dmalloc((size_t)mcap * np * 4);
-  int32_t *M = (int32_t *)e->dmalloc((size_t)np * 4 + 256);
-  float *F = (float *)e->dmalloc((size_t)3 * np * 4);
-  std::vector<float> hf;
-  std::vector<int32_t> hid, hm;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  hipError_t err = hipSuccess;
-  int32_t ovf = 0;
-  double tb = 0.0, tf = 0.0;
-  if (!W || !M || !F) {
-    st = MD_ERR_OOM;
-    goto done;
-  }
-  {
-    int32_t *dovf = M + np;
-    const bool h = half != 0;
-    err = hipEventCreate(&ev[0]);
-    if (err == hipSuccess) err = hipEventCreate(&ev[1]);
-    if (err == hipSuccess) err = hipMemsetAsync(dovf, 0, 4, e->work);
-    for (int k = 0; k < reps && err == hipSuccess; ++k) {
-      float ms = 0.f;
-      err = hipEventRecord(ev[0], e->work);
-      launch_ab_build(h, d.P[pb][0], d.P[pb][1], d.P[pb][2], d.cell, d.cs, n, np, g.G, g.L,
-                      g.rn * g.rn, mcap, W, M, dovf, e->work);
-      if (err == hipSuccess) err = hipGetLastError();
-      if (err == hipSuccess) err = hipEventRecord(ev[1], e->work);
-      if (err == hipSuccess) err = hipEventSynchronize(ev[1]);
-      if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev[0], ev[1]);
-      tb += ms;
-    }
-    if (err == hipSuccess)
-      err = hipMemcpyAsync(&ovf, dovf, 4, hipMemcpyDeviceToHost, e->work);
-    if (err == hipSuccess) err = hipStreamSynchronize(e->work);
-    for (int k = 0; k < reps && err == hipSuccess && ovf == 0; ++k) {
-      float ms = 0.f;
-      if (h) err = hipMemsetAsync(F, 0, (size_t)3 * np * 4, e->work);
-      if (err == hipSuccess) err = hipEventRecord(ev[0], e->work);
-      launch_ab_forces(h, d.P[pb][0], d.P[pb][1], d.P[pb][2], W, M, n, np, g.L, g.rc * g.rc, F,
-                       e->work);
-      if (err == hipSuccess) err = hipGetLastError();
-      if (err == hipSuccess) err = hipEventRecord(ev[1], e->work);
-      if (err == hipSuccess) err = hipEventSynchronize(ev[1]);
-      if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev[0], ev[1]);
-      tf += ms;
-    }
-    if (err == hipSuccess && ovf == 0) {
-      hf.resize((size_t)3 * np);
-      hid.resize(n);
-      hm.resize(n);
-      err = hipMemcpyAsync(hf.data(), F, (size_t)3 * np * 4, hipMemcpyDeviceToHost, e->work);
-      if (err == hipSuccess)
-        err = hipMemcpyAsync(hid.data(), d.id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
-      if (err == hipSuccess)
-        err = hipMemcpyAsync(hm.data(), M, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
-      if (err == hipSuccess) err = hipStreamSynchronize(e->work);
-    }
-    if (err != hipSuccess) {
-      st = e->fail("newton3 a/b", err);
-      goto done;
-    }
-    if (ovf != 0) {
-      st = MD_ERR_NEBR_OVERFLOW;
-      goto done;
-    }
-    int64_t tot = 0;
-    for (int p = 0; p < n; ++p) {
-      tot += hm[p];
-      const int i = hid[p];
-      if (force && i >= 0 && i < n)
-        for (int a = 0; a < 3; ++a) force[3 * (size_t)i + a] = hf[(size_t)a * np + p];
-    }
-    if (n_entries) *n_entries = tot;
-    if (build_ms) *build_ms = tb / reps;
-    if (force_ms) *force_ms = tf / reps;
-  }
-done:
-  for (hipEvent_t x : ev)
-    if (x) (void)hipEventDestroy(x);
-  (void)hipStreamSynchronize(e->work);
-  e->dfree(W);
-  e->dfree(M);
-  e->dfree(F);
+  st = newton3_ab(e, r, half != 0, reps, force, build_ms, force_ms, n_entries);
   md_status st2 = e->leave();
   return st != MD_OK ? st : st2;
 }
