@@ -32,7 +32,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "atom-steps/s soft-sphere ρ=0.8 (single vs batched); p50/p99 request latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sp256000_traffic.json")
+TRAFFIC_FILES = {n: os.path.join(ROOT, "profiles", f"k_step_{n}_traffic.json")
+                 for n in ("sp256000", "sp4000000")}
 KERNEL_SRC = os.path.join(ROOT, "paper_0911_5631_amd", "csrc", "md_kernels.hip")
 
 
@@ -59,11 +60,15 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_per_launch():
-    """HBM bytes per force-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+def traffic_per_launch(n_atoms: int):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary of this workload size, if it was taken on the current kernel
+    source."""
+    path = TRAFFIC_FILES.get(f"sp{n_atoms}")
+    if path is None:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -498,7 +503,7 @@ def main() -> int:
     avg_s = kern_ms * 1e-3 / max(launches, 1)
     bytes_launch = step_bytes_per_atom(mean_m, rebuild_frac) * n
     achieved = bytes_launch / avg_s / 1e9
-    traffic = traffic_per_launch()
+    traffic = traffic_per_launch(n)
     model_b = model_bytes_per_atom_step(mean_m, rebuild_frac)
     out = {
         "metric": METRIC,
