@@ -342,9 +342,13 @@ def _run_batch(specs, steps_per_run=64, stagger=None):
         first, later = pending[:stagger], pending[stagger:]
     else:
         first, later = pending, []
+    def admit(k):
+        pos, vel, L, n_steps = specs[k][:4]
+        prm = specs[k][4] if len(specs[k]) > 4 else {"shell": 0.4}
+        slots[b.admit(pos, vel, L, n_steps, **prm)] = k
+
     for k in first:
-        pos, vel, L, n_steps = specs[k]
-        slots[b.admit(pos, vel, L, n_steps, shell=0.4)] = k
+        admit(k)
     out = {}
     runs = 0
     while len(out) < len(specs):
@@ -352,8 +356,7 @@ def _run_batch(specs, steps_per_run=64, stagger=None):
         runs += 1
         if runs == 1:
             for k in later:
-                pos, vel, L, n_steps = specs[k]
-                slots[b.admit(pos, vel, L, n_steps, shell=0.4)] = k
+                admit(k)
         for slot in b.poll():
             if slot in slots and slots[slot] not in out:
                 p, v, step = b.get_state(slot)
@@ -383,6 +386,38 @@ def test_batch_equals_solo_bit_for_bit():
         assert gpr["n_rebuilds"] == pr["n_rebuilds"]
         assert gpr["pe"] == pr["pe"] and gpr["ke"] == pr["ke"]
         s.close()
+
+
+def test_mixed_batch_equals_solo_bit_for_bit():
+    """One batch holding FP32 and FP64 replicas of both potentials (the
+    soft-sphere cutoff and LJ at r_c = 2.5 with a wider shell): each
+    precision is its own step-kernel launch over the shared tables, each
+    replica its own cutoff and list radius, and every trajectory equals the
+    same system run alone."""
+    specs = []
+    for k, (prec, lj) in enumerate([("fp32", False), ("fp64", False), ("fp32", True),
+                                    ("fp64", True), ("fp64", False)]):
+        if lj:
+            pos, L = I.sc_lattice(11 + k, 0.38)
+            pos = I.jitter(pos, L, 0.1, 60 + k)
+            vel = I.random_velocities(len(pos), 1.2, 70 + k)
+            prm = {"r_cut": 2.5, "shell": 0.8, "precision": prec}
+        else:
+            pos, vel, L = fluid(4 + k, seed=80 + k)
+            prm = {"shell": 0.4, "precision": prec}
+        specs.append((pos, vel, L, 90 + 17 * k, prm))
+    got = _run_batch(specs, steps_per_run=32, stagger=3)
+    for k, (pos, vel, L, steps, prm) in enumerate(specs):
+        s = _system(pos, vel, L, **prm)
+        s.step(steps)
+        p, v, _, step = s.get_state()
+        pr = s.props()
+        s.close()
+        gp, gv, gstep, gpr = got[k]
+        assert gstep == step == steps
+        assert np.array_equal(gp, p) and np.array_equal(gv, v), (k, prm)
+        assert gpr["n_rebuilds"] == pr["n_rebuilds"] and gpr["n_rebuilds"] > 0
+        assert gpr["pe"] == pr["pe"] and gpr["ke"] == pr["ke"]
 
 
 def test_batch_admission_respects_budget():
