@@ -248,6 +248,33 @@ struct md_batch {
 
 namespace {
 
+// One ABI call's stay on the library's stream.  enter() orders that stream
+// after the caller's; leave() orders the caller's stream after the work the
+// call enqueued and reports its status, and an early return (an error) leaves
+// through the destructor, so the caller's stream is ordered on every exit.
+class Visit {
+ public:
+  explicit Visit(Engine *e) : e_(e) {}
+  Visit(const Visit &) = delete;
+  Visit &operator=(const Visit &) = delete;
+  ~Visit() {
+    if (open_) (void)e_->leave();
+  }
+  md_status enter() {
+    const md_status st = e_->enter();
+    open_ = st == MD_OK;
+    return st;
+  }
+  md_status leave() {
+    open_ = false;
+    return e_->leave();
+  }
+
+ private:
+  Engine *e_;
+  bool open_ = false;
+};
+
 md_status engine_init(Engine *e, int max_slots, const md_allocator *a, void *stream) {
   e->max_slots = max_slots;
   e->rep.assign(max_slots, nullptr);
@@ -1081,13 +1108,14 @@ md_status md_bin_cells(md_system *s) {
   md_status st = sys_ok(s);
   if (st != MD_OK) return st;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
   // wrap + bin + sort the held state; the new storage order invalidates the
   // list and the stored forces, so both are evaluated again
   if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
   if ((st = set_force_step(e, 0)) != MD_OK) return st;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_build_nebr(md_system *s) {
@@ -1095,23 +1123,25 @@ md_status md_build_nebr(md_system *s) {
   if (st != MD_OK) return st;
   Engine *e = s->e;
   if (e->rep[0]->g.cell_only) return MD_ERR_STATE;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
   // the list is built from the contiguous cell ranges of freshly sorted atoms
   if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
   if ((st = set_force_step(e, 0)) != MD_OK) return st;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_forces(md_system *s) {
   md_status st = sys_ok(s);
   if (st != MD_OK) return st;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
   launch_step(e->tables(), e->grid, 0, MODE_FORCES, 0, -1, e->prec, e->work, false, e->mix);
   if ((st = sync_system(e)) != MD_OK) return st;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_step(md_system *s, int64_t n_steps) {
@@ -1120,7 +1150,8 @@ md_status md_step(md_system *s, int64_t n_steps) {
   if (n_steps < 0) return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
   if (n_steps == 0) return MD_OK;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   const int64_t from = e->host_target;
   const int64_t to = from + n_steps;
   Tables T = e->tables();
@@ -1129,7 +1160,7 @@ md_status md_step(md_system *s, int64_t n_steps) {
   if ((st = e->check("kick")) != MD_OK) return st;
   if ((st = run_steps(e, from, to)) != MD_OK) return st;
   e->host_target = to;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_props(md_system *s, md_props_t *out) {
@@ -1137,11 +1168,12 @@ md_status md_props(md_system *s, md_props_t *out) {
   if (st != MD_OK) return st;
   if (!out) return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   st = sync_system(e);
   if (st == MD_OK || st == MD_ERR_NONFINITE || st == MD_ERR_ATOM_ESCAPED)
     fill_props(e->rep[0], e->h_ctl[0], out);
-  md_status st2 = e->leave();
+  md_status st2 = v.leave();
   return st != MD_OK ? st : st2;
 }
 
@@ -1149,21 +1181,23 @@ md_status md_get_state(md_system *s, double *pos, double *vel, double *force, in
   md_status st = sys_ok(s);
   if (st != MD_OK) return st;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
   if ((st = fetch(e, 0, pos, vel, force, nullptr, nullptr, nullptr)) != MD_OK) return st;
   if (step) *step = e->h_ctl[0].done;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_get_atom_energies(md_system *s, double *u_atom, double *w_atom) {
   md_status st = sys_ok(s);
   if (st != MD_OK) return st;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
   if ((st = fetch(e, 0, nullptr, nullptr, nullptr, u_atom, w_atom, nullptr)) != MD_OK) return st;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_set_state(md_system *s, const double *pos, const double *vel) {
@@ -1171,7 +1205,8 @@ md_status md_set_state(md_system *s, const double *pos, const double *vel) {
   if (st != MD_OK) return st;
   if (!pos || !vel) return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   st = sync_system(e);
   if (st != MD_OK && st != MD_ERR_NONFINITE && st != MD_ERR_ATOM_ESCAPED) return st;
   Replica *r = e->rep[0];
@@ -1188,7 +1223,7 @@ md_status md_set_state(md_system *s, const double *pos, const double *vel) {
     return e->fail("clear ring");
   e->host_target = step;
   if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_adjust_temp(md_system *s, double temperature) {
@@ -1196,7 +1231,8 @@ md_status md_adjust_temp(md_system *s, double temperature) {
   if (st != MD_OK) return st;
   if (!(temperature > 0) || !std::isfinite(temperature)) return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   // the held state is clean after every md_step that met no error; the
   // kernels skip a replica that is not (its error is reported by the next
   // synchronising call)
@@ -1204,14 +1240,15 @@ md_status md_adjust_temp(md_system *s, double temperature) {
   launch_props(T, -1, e->work);
   launch_adjust(T, e->grid, -1, temperature, e->work);
   if ((st = e->check("adjust launches")) != MD_OK) return st;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_block_begin(md_system *s) {
   md_status st = sys_ok(s);
   if (st != MD_OK) return st;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
   Replica *r = e->rep[0];
   const Layout l = layout(r->g);
@@ -1219,7 +1256,7 @@ md_status md_block_begin(md_system *s) {
     return e->fail("clear block sums");
   e->accum = true;
   e->acc_from = e->h_ctl[0].done;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_block_end(md_system *s, md_block_t *out) {
@@ -1227,7 +1264,8 @@ md_status md_block_end(md_system *s, md_block_t *out) {
   if (st != MD_OK) return st;
   if (!out) return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   st = sync_system(e);
   if (st != MD_OK && st != MD_ERR_NONFINITE && st != MD_ERR_ATOM_ESCAPED) return st;
   Replica *r = e->rep[0];
@@ -1246,7 +1284,7 @@ md_status md_block_end(md_system *s, md_block_t *out) {
     out->nebr_per_atom = r->g.cell_only ? 0.0 : c.acc_sum[3] / (double)steps / n;
   }
   e->accum = false;
-  md_status st2 = e->leave();
+  md_status st2 = v.leave();
   return st != MD_OK ? st : st2;
 }
 
@@ -1280,7 +1318,8 @@ md_status md_set_species(md_system *s, int32_t n_species, const int32_t *species
     }
   for (int64_t i = 0; i < n; ++i)
     if (species[i] < 0 || species[i] >= ns) return MD_ERR_INVALID_ARG;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
   if (!r->mixbuf) {
     const size_t bytes = round_up(sizeof(PairTab), 256) + (size_t)2 * r->g.npad * 4;
@@ -1301,7 +1340,7 @@ md_status md_set_species(md_system *s, int32_t n_species, const int32_t *species
   // the held state with its new forces (sorted again, as md_bin_cells)
   if ((st = evaluate_clean(e, -1, MODE_FORCES, 1)) != MD_OK) return st;
   if ((st = set_force_step(e, 0)) != MD_OK) return st;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
@@ -1312,10 +1351,11 @@ md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
   Engine *e = s->e;
   Replica *r = e->rep[0];
   if (r->g.cell_only || r->nsp > 0) return MD_ERR_STATE;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
   st = newton3_ab(e, r, half != 0, reps, force, build_ms, force_ms, n_entries);
-  md_status st2 = e->leave();
+  md_status st2 = v.leave();
   return st != MD_OK ? st : st2;
 }
 
@@ -1324,18 +1364,20 @@ md_status md_get_cells(md_system *s, int32_t *cell_of_atom) {
   if (st != MD_OK) return st;
   if (!cell_of_atom) return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
   if ((st = fetch(e, 0, nullptr, nullptr, nullptr, nullptr, nullptr, cell_of_atom)) != MD_OK)
     return st;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_get_bins(md_system *s, int32_t *order, int32_t *cell_start) {
   md_status st = sys_ok(s);
   if (st != MD_OK) return st;
   Engine *e = s->e;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
   Replica *r = e->rep[0];
   const SlotDev &d = r->dev[held_variant(e->h_ctl[0])];
@@ -1346,7 +1388,7 @@ md_status md_get_bins(md_system *s, int32_t *order, int32_t *cell_start) {
                          e->work);
   if (err == hipSuccess) err = hipStreamSynchronize(e->work);
   if (err != hipSuccess) return e->fail("get bins", err);
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_get_pairs(md_system *s, int64_t cap, int32_t *pi, int32_t *pj, int64_t *n_out) {
@@ -1356,7 +1398,8 @@ md_status md_get_pairs(md_system *s, int64_t cap, int32_t *pi, int32_t *pj, int6
   Engine *e = s->e;
   Replica *r = e->rep[0];
   if (r->g.cell_only) return MD_ERR_STATE;
-  if ((st = e->enter()) != MD_OK) return st;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
   const SlotDev &d = r->dev[held_variant(e->h_ctl[0])];
   const int64_t n = r->g.n;
@@ -1395,7 +1438,7 @@ md_status md_get_pairs(md_system *s, int64_t cap, int32_t *pi, int32_t *pj, int6
     }
   }
   *n_out = k;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_profile(md_system *s, int32_t enable) {
@@ -1502,7 +1545,8 @@ md_status md_batch_admit(md_batch *b, const md_params *p, const double *pos, con
       break;
     }
   if (s < 0) return MD_ERR_NO_SLOT;
-  md_status st = e->enter();
+  Visit v(e);
+  md_status st = v.enter();
   if (st != MD_OK) return st;
   Replica *r = nullptr;
   if ((st = alloc_replica(e, p, &r)) != MD_OK) return st;
@@ -1543,24 +1587,26 @@ md_status md_batch_admit(md_batch *b, const md_params *p, const double *pos, con
     return st;
   }
   *slot = s;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_batch_run(md_batch *b) {
   if (!b || !b->e) return MD_ERR_INVALID_ARG;
   Engine *e = b->e;
-  md_status st = e->enter();
+  Visit v(e);
+  md_status st = v.enter();
   if (st != MD_OK) return st;
   launch_kick(e->tables(), e->grid, e->work);
   if ((st = e->check("kick")) != MD_OK) return st;
   if ((st = replay(e, e->steps_per_run)) != MD_OK) return st;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_batch_poll(md_batch *b, int32_t *done, int32_t cap, int32_t *n_done) {
   if (!b || !b->e || !n_done || cap < 0 || (cap > 0 && !done)) return MD_ERR_INVALID_ARG;
   Engine *e = b->e;
-  md_status st = e->enter();
+  Visit v(e);
+  md_status st = v.enter();
   if (st != MD_OK) return st;
   if ((st = settle(e)) != MD_OK) return st;
   int k = 0;
@@ -1574,7 +1620,7 @@ md_status md_batch_poll(md_batch *b, int32_t *done, int32_t cap, int32_t *n_done
     }
   }
   *n_done = k;
-  return e->leave();
+  return v.leave();
 }
 
 md_status md_batch_props(md_batch *b, int32_t slot, md_props_t *out) {
