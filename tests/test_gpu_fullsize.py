@@ -119,6 +119,38 @@ def test_lj_full_size_sampled_parity():
     s.close()
 
 
+def test_largest_system_the_index_width_allows():
+    """The largest fcc system under the 25-bit storage index: n_c = 203,
+    33 461 708 atoms (2^25 - 1 is the limit), 13.5 GB on the device.  After
+    steps with a rebuild, sampled forces and energies against the oracle's
+    brute-force sums, half of the sample stored at positions >= 2^24 (the
+    top index bit set in their list entries); momentum as at 4 x 10^6."""
+    from paper_0911_5631_amd.md import md_query_bytes, make_params
+    from paper_0911_5631_amd._lib import MDError
+    pos, L = I.fcc_lattice(203, 0.8)
+    n = len(pos)
+    assert n == 33_461_708 and n <= (1 << 25) - 1
+    with pytest.raises(MDError):
+        md_query_bytes(make_params(1 << 25, L, shell=0.4))
+    vel = I.random_velocities(n, 1.0, 19)
+    s = _system(pos, vel, L, shell=0.4, dt=0.005)
+    del pos
+    s.step(30)
+    pr = s.props()
+    assert pr["step"] == 30 and pr["n_rebuilds"] >= 1
+    order, _ = s.bins()
+    rng = np.random.Generator(np.random.PCG64(20))
+    high = order[rng.choice(np.arange(1 << 24, n), 24, replace=False)]
+    idx = np.unique(np.concatenate([high, rng.choice(n, 24, replace=False)])).astype(np.int64)
+    pos, vel, force, _ = s.get_state()
+    assert np.isfinite(pos).all() and np.isfinite(force).all()
+    u_ref = _check_sampled_forces(pos, force, L, idx)
+    u_atom, _ = s.atom_energies()
+    s.close()
+    assert float(np.abs(u_atom[idx] - u_ref).max()) <= 1e-6 * max(1.0, float(np.abs(u_ref).max()))
+    assert float(np.abs(vel.sum(0)).max()) <= 1e-6 * n ** 0.5 * 30
+
+
 def test_single_atom_and_pair():
     # one atom: no pairs, no force, nothing to do but drift
     L = 5.0
