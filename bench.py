@@ -372,8 +372,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample (0: skip)")
     ap.add_argument("--workload", default="sp_256k",
-                    choices=["sp_256k", "sp_4m", "sp_small", "batch", "served", "equil", "lj",
-                             "newton3", "mixture"],
+                    choices=["sp_256k", "sp_4m", "sp_33m", "sp_small", "batch", "served",
+                             "equil", "lj", "newton3", "mixture"],
                     help="single system (default sp_256k); 'batch' / 'served' run only the full "
                          "batched-replica or served-stream workload and print its JSON line; "
                          "'equil' the paper's system S with equilibration and block averages; "
@@ -467,7 +467,8 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst, flush
-    wl = {"sp_256k": I.sp_256k, "sp_4m": I.sp_4m, "sp_small": I.sp_small_cells}[args.workload]()
+    wl = {"sp_256k": I.sp_256k, "sp_4m": I.sp_4m, "sp_33m": I.sp_33m,
+          "sp_small": I.sp_small_cells}[args.workload]()
     n = wl.n
     s = System(wl.pos, wl.vel, wl.box, shell=wl.shell, dt=wl.dt, precision=wl.precision)
     print(f"# created {wl.name}: N={n} L={wl.box:.4f}", file=sys.stderr, flush=True)

@@ -183,6 +183,13 @@ def sp_4m() -> System:
                       precision="fp32", seed=3)
 
 
+def sp_33m() -> System:
+    """N = 33 461 708 (fcc 203^3 x 4: the largest fcc start under the 25-bit
+    storage index, 2^25 - 1 atoms), rho 0.8, T 1, shell 0.4, 500 steps."""
+    return fcc_system("sp_33461708_nebr_fp32", 203, 0.8, 1.0, shell=0.4, steps=500,
+                      precision="fp32", seed=4)
+
+
 def _replica_seed(seed: int, index: int) -> int:
     # SplitMix64-style mixing of (seed, index) into an independent stream seed.
     z = (seed * 0x9E3779B97F4A7C15 + (index + 1) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
