@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "atom-steps/s soft-sphere ρ=0.8 (single vs batched); p50/p99 request latency"
 TRAFFIC_FILES = {n: os.path.join(ROOT, "profiles", f"k_step_{n}_traffic.json")
-                 for n in ("sp256000", "sp4000000")}
+                 for n in ("sp256000", "sp4000000", "sp33461708")}
 KERNEL_SRC = os.path.join(ROOT, "paper_0911_5631_amd", "csrc", "md_kernels.hip")
 
 
