@@ -46,6 +46,8 @@ constexpr int WSTRIDE = 1 + 3 * NWIN;  // ints per tile: count, then (start, len
 constexpr int NPART = 8;           // doubles per tile in the property partials
 constexpr int NACC = 4;            // doubles per tile in the block accumulators
 constexpr int MAX_GRID = 2048;     // persistent-style grid bound (256 CUs x 8)
+constexpr int SORT_GRID = 512;     // sort workgroups of a single system (fewer, fuller
+                                   // workgroups: idle launches cost less)
 constexpr int OVF_CAP = 4096;      // per-set overflow list of cell-layer rows
 constexpr int VSPREAD = 32;        // slots of each max-speed ring entry (one per 128-byte line)
 constexpr int MAXSP = 4;           // species of a mixture

@@ -484,7 +484,7 @@ md_status upload_tables(Engine *e) {
   if (err != hipSuccess) return e->fail("upload tables", err);
   if (!e->batch) {
     e->grid = std::max(1, std::min(nt, MAX_GRID));
-    e->cgrid = std::max(1, std::min(nct * split, MAX_GRID));
+    e->cgrid = std::max(1, std::min(nct * split, SORT_GRID));
   }
   return MD_OK;
 }

@@ -400,17 +400,29 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
       }
       skip = false;
     }
-    if (skip) continue;
+    // one replica: its units are all the launch has, so a workgroup with
+    // nothing to do for it stops instead of visiting its other units (an
+    // idle launch then costs one unit per workgroup)
+    const bool solo = T.nslots == 1;
+    if (skip) {
+      if (solo) break;
+      continue;
+    }
     if (mode == MODE_STEP) {
       if (t == S0.ctile_off && sp == 0 && threadIdx.x == 0) {
-        // the one writer of these ring slots for step k
+        // the one writer of these ring slots for step k (with one replica
+        // that is unit 0, the first unit of its workgroup, so no workgroup
+        // stops before it)
         C.rb_ring[mod3(k)] = rebuild ? 1 : 0;
         if (!S0.cell_only) {
           C.disp_ring[mod3(k - 1)] = d1;
           if (rebuild && k != C.force_step) C.n_rebuilds += 1;
         }
       }
-      if (!rebuild) continue;
+      if (!rebuild) {
+        if (solo) break;
+        continue;
+      }
     }
     SlotC &S = slot(T, 2 * r + var);
     SlotC &D = slot(T, 2 * r + (var ^ 1));
