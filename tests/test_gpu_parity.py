@@ -420,6 +420,35 @@ def test_mixed_batch_equals_solo_bit_for_bit():
         assert gpr["pe"] == pr["pe"] and gpr["ke"] == pr["ke"]
 
 
+def test_one_slot_batch_reused_equals_solo():
+    """A batch of one slot (its sort then takes the single-system path: idle
+    workgroups stop after their first unit) run twice, the slot released and
+    re-admitted in between, equals the systems run alone."""
+    from paper_0911_5631_amd.md import Batch
+    specs = [fluid(6, seed=71) + (170,), fluid(5, seed=72) + (90,)]
+    b = Batch(1 << 31, 1, 32)
+    got = []
+    for pos, vel, L, steps in specs:
+        slot = b.admit(pos, vel, L, steps, shell=0.4)
+        assert slot == 0
+        for _ in range(20):
+            b.run()
+            if b.poll():
+                break
+        got.append(b.get_state(slot) + (b.props(slot),))
+        b.release(slot)
+    b.close()
+    for (pos, vel, L, steps), (gp, gv, gstep, gpr) in zip(specs, got):
+        s = _system(pos, vel, L, shell=0.4)
+        s.step(steps)
+        p, v, _, step = s.get_state()
+        pr = s.props()
+        s.close()
+        assert gstep == step == steps
+        assert np.array_equal(gp, p) and np.array_equal(gv, v)
+        assert gpr["n_rebuilds"] == pr["n_rebuilds"] > 0 and gpr["pe"] == pr["pe"]
+
+
 def test_batch_admission_respects_budget():
     from paper_0911_5631_amd.md import Batch, md_query_bytes, make_params
     pos, L = I.fcc_lattice(6, 0.8)
