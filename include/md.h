@@ -35,7 +35,8 @@
  *     hipFree).  Host buffers passed in are never retained.
  *   - Streams: device work is ordered after everything already enqueued on
  *     the HIP stream given at creation (NULL: the null stream), and later
- *     work on that stream waits for it.  Calls marked "async" return before
+ *     work on that stream waits for it (also after a call that returns an
+ *     error).  Calls marked "async" return before
  *     the device work completes; calls marked "sync" wait for it.
  *   - Errors found on the device (an escaped atom, a non-finite coordinate)
  *     are latched in the system, stop its device work at the step where
