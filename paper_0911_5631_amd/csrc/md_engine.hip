@@ -848,7 +848,7 @@ void fill_props(const Replica *r, const CtlDev &c, md_props_t *o) {
   o->max_nebr = c.max_m;
   o->max_cell = c.max_h;
   o->cells_per_edge = r->g.G;
-  // displacement accumulated through the held step and the rule's verdict
+  // displacement accumulated through the held step and the rule's decision
   // for the next one (the step kernel recomputes the same from the rings)
   if (!r->g.cell_only && c.clean) {
     const int64_t k = c.done + 1;
