@@ -137,7 +137,7 @@ def served(n_requests: int, rate: float, k_hi: int, steps_lo: int, steps_hi: int
 
 
 def equilibrated(shell: float) -> dict:
-    """The paper's system S run as in Table 4: the Sec. 4 equilibration
+    """The paper's system S run as in Table 4: the Sec. 5.1 equilibration
     (velocities adjusted every 20 steps during the first 500), then a block
     average over steps 1001-2000, all on the device; then 1000 plain steps
     (no block) for the cost of summing the properties every step."""
@@ -178,7 +178,7 @@ def equilibrated(shell: float) -> dict:
 
 
 def lennard_jones(rc: float, n_edge: int, steps: int) -> dict:
-    """The paper's LJ system (Sec. 4: rho 0.38, T 1.2, shell 0.8, simple cubic
+    """The paper's LJ system (Sec. 5.1: rho 0.38, T 1.2, shell 0.8, simple cubic
     start) with cutoff rc, no shift: 500 steps of equilibration untimed, then
     `steps` timed steps."""
     import torch

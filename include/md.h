@@ -5,24 +5,24 @@
  * programmable graphics processor" (arXiv:0911.5631).  The library advances
  * atoms interacting through the soft-sphere potential -- Eq. (1), the
  * Lennard-Jones form, truncated at r_c = 2^(1/6) with the constant epsilon
- * added so that u(r_c) = 0 (Sec. 2.1) -- in a periodic cube centred at the
+ * added so that u(r_c) = 0 (Sec. 3.1) -- in a periodic cube centred at the
  * origin, in reduced units sigma = epsilon = m = 1.
  *
- * The path per time step (Sec. 2.1, loop steps (a)-(e)):
+ * The path per time step (Sec. 3.1, loop steps (a)-(e)):
  *   (a) half-step velocity update and full-step position update (leapfrog);
  *   (b) when a rebuild is due: periodic wrap, cell binning (cell assignment
- *       and layer assignment, Secs. 2.2 and 2.4), reordering of the atoms
- *       into cell order (Sec. 2.5; done at every rebuild, as a stable
+ *       and layer assignment, Secs. 3.2 and 3.4), reordering of the atoms
+ *       into cell order (Sec. 3.5; done at every rebuild, as a stable
  *       counting sort) and the neighbour-matrix build over 27 cells without
- *       Newton's third law (Secs. 2.3-2.4);
- *   (c) forces and potential energy from the neighbour matrix (Sec. 2.4);
+ *       Newton's third law (Secs. 3.3-3.4);
+ *   (c) forces and potential energy from the neighbour matrix (Sec. 3.4);
  *   (d) second half-step velocity update;
  *   (e) kinetic energy, maximum speed and the rebuild decision: the list is
  *       rebuilt when the accumulated sum of vmax*dt exceeds delta/2
- *       (Sec. 2.1);
+ *       (Sec. 3.1);
  *   (f) during equilibration, the velocity adjustment (md_adjust_temp);
  *       properties averaged over blocks of steps (md_block_begin/end).
- * With shell == 0 the library runs the plain cell method instead (Sec. 2.1):
+ * With shell == 0 the library runs the plain cell method instead (Sec. 3.1):
  * every step re-bins and evaluates forces straight from the 27 neighbouring
  * cells, with no stored list.
  *
@@ -145,7 +145,7 @@ typedef struct {
 const char *md_status_string(md_status s);
 
 /* Cells per edge G for these parameters (floor(L / r_n), or its even floor
- * with MD_EVEN_CELLS), without creating anything.  Sec. 2.1 defines G. */
+ * with MD_EVEN_CELLS), without creating anything.  Sec. 3.1 defines G. */
 md_status md_cells_per_edge(const md_params *p, int32_t *G);
 
 /* Device bytes md_create would allocate for these parameters (for admission
@@ -163,15 +163,15 @@ md_status md_create(const md_params *p, const double *pos, const double *vel,
                     const md_allocator *a, void *hip_stream, md_system **out);
 
 /* Periodic wrap, cell assignment and stable cell-order reordering (cell
- * assignment Sec. 2.2 and its listing, layer assignment Sec. 2.4, reordering
- * Sec. 2.5) of the held state: atoms end up stored cell by cell, and within
+ * assignment Sec. 3.2 and its listing, layer assignment Sec. 3.4, reordering
+ * Sec. 3.5) of the held state: atoms end up stored cell by cell, and within
  * a cell in their previous storage order.  The new storage order is then
  * evaluated again (neighbour matrix, forces, properties; the forces can
  * differ from the previous ones in the last bits, through the summation
  * order), and the displacement rule restarts from this state.  Sync. */
 md_status md_bin_cells(md_system *s);
 
-/* Build the neighbour matrix W[m][i] (Sec. 2.4) at the held state: for
+/* Build the neighbour matrix W[m][i] (Sec. 3.4) at the held state: for
  * every atom, all atoms j != i of the 27 surrounding cells with r^2 < r_n^2,
  * visited cell by cell (offsets z-major, x fastest) and in storage order
  * within a cell.  The list is built from freshly sorted cells, so this also
@@ -180,7 +180,7 @@ md_status md_bin_cells(md_system *s);
 md_status md_build_nebr(md_system *s);
 
 /* Forces, per-atom energies and virials at the held positions from the
- * current neighbour matrix (Sec. 2.4 force algorithm; cell method when
+ * current neighbour matrix (Sec. 3.4 force algorithm; cell method when
  * shell == 0), plus the properties.  Stores the forces used by the next
  * md_step.  Sync. */
 md_status md_forces(md_system *s);
@@ -194,7 +194,7 @@ md_status md_step(md_system *s, int64_t n_steps);
  * Sync; returns latched device errors. */
 md_status md_props(md_system *s, md_props_t *out);
 
-/* Several species, the extension the paper names at the end of Sec. 2
+/* Several species, the extension the paper names in Sec. 3.5
  * (with no parameters there): species[i] in [0, n_species) for every atom
  * (original order), and per species pair (a, b) -- row-major n_species x
  * n_species arrays, symmetric -- epsilon >= 0, sigma > 0, the cutoff
@@ -211,8 +211,8 @@ md_status md_set_species(md_system *s, int32_t n_species, const int32_t *species
                          const double *epsilon, const double *sigma, const double *r_cut,
                          const double *shift);
 
-/* Step (f) of the loop (Sec. 2.1), used during the equilibration period of
- * Sec. 4 (every 20 steps for the first 500): scale every velocity of the
+/* Step (f) of the loop (Sec. 3.1), used during the equilibration period of
+ * Sec. 5.1 (every 20 steps for the first 500): scale every velocity of the
  * held state by one factor so that sum v^2 = 3 (N - 1) T, T = temperature
  * (with the centre of mass at rest 3 (N - 1) degrees of freedom remain).
  * Call it after md_step; the factor comes from the kinetic energy of (e) of
@@ -222,7 +222,7 @@ md_status md_set_species(md_system *s, int32_t n_species, const int32_t *species
  * positive and finite.  Async. */
 md_status md_adjust_temp(md_system *s, double temperature);
 
-/* Block averages (Sec. 4 evaluates its properties as means over blocks of
+/* Block averages (Sec. 5.1 evaluates its properties as means over blocks of
  * 1000 steps).  md_block_begin starts a block at the held step: every
  * following step of md_step sums its kinetic and potential energy, virial
  * and list length on the device (per tile, in a fixed order, so the result
@@ -272,9 +272,9 @@ md_status md_profile(md_system *s, int32_t enable);
 md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms);
 
 /* Newton's-third-law A/B of the force phase.  The paper drops Newton's
- * third law on the GPU (Sec. 2.3: full lists, each atom sums its own force)
+ * third law on the GPU (Sec. 3.3: full lists, each atom sums its own force)
  * where the CPU keeps each pair once and adds the reaction to the partner
- * (Sec. 2.2).  At the held state, after a fresh sort (as md_bin_cells), this
+ * (Sec. 3.2).  At the held state, after a fresh sort (as md_bin_cells), this
  * builds a plain neighbour list over the sorted cells -- storage-index
  * entries, r^2 < r_n^2 in FP64 -- full (every j != i) or half (half != 0:
  * j > i, each pair once), then evaluates the pair forces (FP32 on FP64

@@ -12,20 +12,20 @@
  *
  * What it computes, and where the paper defines it:
  *   - the soft-sphere potential: Eq. (1) truncated at r_c = 2^(1/6) with the
- *     constant epsilon added so that u(r_c) = 0 (Sec. 2.1, Eq. 1 and the
+ *     constant epsilon added so that u(r_c) = 0 (Sec. 3.1, Eq. 1 and the
  *     sentence after it); reduced units sigma = epsilon = m = 1;
  *   - region geometry: edge L, cell grid G = floor(L / r_n) per edge, cell
- *     edge w = L / G, region centred at the origin (Sec. 2.1);
- *   - cell assignment by linked lists (Sec. 2.2, first algorithm);
+ *     edge w = L / G, region centred at the origin (Sec. 3.1);
+ *   - cell assignment by linked lists (Sec. 3.2, first algorithm);
  *   - the half neighbour-pair list over 14 cells with periodic image codes
- *     (Sec. 2.2, second algorithm) and the Newton's-third-law force loop over
- *     it (Sec. 2.2, third algorithm);
- *   - layer assignment (Sec. 2.4, first algorithm) and the cell-order
- *     reordering scan of the cell-layer matrix (Sec. 2.5, reorder algorithm),
+ *     (Sec. 3.2, second algorithm) and the Newton's-third-law force loop over
+ *     it (Sec. 3.2, third algorithm);
+ *   - layer assignment (Sec. 3.4, first algorithm) and the cell-order
+ *     reordering scan of the cell-layer matrix (Sec. 3.5, reorder algorithm),
  *     used to state what a stable cell binning must produce;
  *   - the leapfrog MD loop, steps (a)-(e), with the neighbour list rebuilt
- *     once the accumulated maximum displacement passes delta/2 (Sec. 2.1), and
- *     step (f), the velocity adjustment of the equilibration period (Sec. 4);
+ *     once the accumulated maximum displacement passes delta/2 (Sec. 3.1), and
+ *     step (f), the velocity adjustment of the equilibration period (Sec. 5.1);
  *   - brute-force O(N^2) definitions of the pair set and of the forces over
  *     all 27 periodic images, used to pin the cell algorithms above.
  *
@@ -79,7 +79,7 @@ void or_pair_potential(double r, double rc, double ushift, double *u, double *fr
 }
 
 /* ------------------------------------------------------------------------ */
-/* Several species: the extension the paper names at the end of Sec. 2 (no  */
+/* Several species: the extension the paper names in Sec. 3.5 (no  */
 /* parameters given there).  Each species pair (a, b) has its own epsilon,  */
 /* sigma, cutoff and energy shift: u = 4 eps ((sigma/r)^12 - (sigma/r)^6) + */
 /* shift inside the cutoff, i.e. Eq. (1) in units of sigma_ab and eps_ab.   */
@@ -105,7 +105,7 @@ static double pair_fu_mix(const or_mix *mx, int k, double s, double *u)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Geometry (Sec. 2.1)                                                       */
+/* Geometry (Sec. 3.1)                                                       */
 /* ------------------------------------------------------------------------ */
 
 /* Cells per edge: floor(L / r_n); with even != 0, the largest even number
@@ -151,9 +151,9 @@ void or_cell_ids(int64_t n, const double *x, const double *y, const double *z,
     }
 }
 
-/* Layer assignment (Sec. 2.4): k_c counts the occupants of cell c seen so
+/* Layer assignment (Sec. 3.4): k_c counts the occupants of cell c seen so
  * far in index order, l_i is atom i's 0-based layer.  Then the reorder scan
- * (Sec. 2.5): H_{c,l} = i, read in cell order and, within a cell, in layer
+ * (Sec. 3.5): H_{c,l} = i, read in cell order and, within a cell, in layer
  * order, gives the new storage order.  Outputs: layer[n], order[n] (order[p]
  * = index of the atom stored at position p after reordering), cell_start
  * [N_c + 1] (first position of each cell) and the layer count N_l. */
@@ -190,7 +190,7 @@ int or_layers_reorder(int64_t n, const int32_t *cell, int G, int32_t *layer,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Linked-list cells and the 14-cell half pair list (Sec. 2.2)               */
+/* Linked-list cells and the 14-cell half pair list (Sec. 3.2)               */
 /* ------------------------------------------------------------------------ */
 
 /* The 14 offsets: the cell itself and the 13 with (oz, oy, ox)
@@ -227,7 +227,7 @@ static int build_linked_cells(cells_t *cl, int64_t n, const double *x, const dou
     }
     for (int64_t c = 0; c < nc; ++c) cl->head[c] = -1;
     or_cell_ids(n, x, y, z, L, G, cell);
-    for (int64_t i = 0; i < n; ++i) {  /* Sec. 2.2, linked-list assignment */
+    for (int64_t i = 0; i < n; ++i) {  /* Sec. 3.2, linked-list assignment */
         cl->next[i] = cl->head[cell[i]];
         cl->head[cell[i]] = (int32_t)i;
     }
@@ -306,7 +306,7 @@ static void list_visit(void *vctx, int32_t i, int32_t j, const int8_t img[3],
     }
 }
 
-/* Half neighbour-pair list with r^2 < r_n^2 (Sec. 2.2).  img holds, per pair,
+/* Half neighbour-pair list with r^2 < r_n^2 (Sec. 3.2).  img holds, per pair,
  * the image shift of atom j in units of L (-1, 0, +1 per dimension).
  * Returns the number of pairs found; only the first `cap` are stored. */
 int64_t or_pairs_cells(int64_t n, const double *x, const double *y, const double *z,
@@ -400,7 +400,7 @@ static void acc_zero(force_acc *a, int64_t n)
     a->n_inter = 0;
 }
 
-/* Pair-list force loop with Newton's third law (Sec. 2.2): for each stored
+/* Pair-list force loop with Newton's third law (Sec. 3.2): for each stored
  * pair with r^2 < r_c^2, f_i += f d, f_j -= f d, U += u, W += f r^2.
  * With mix (may be NULL) the pair's own cutoff and parameters apply (rc is
  * then the largest cutoff).  The cell and brute-force versions below take
@@ -444,7 +444,7 @@ static void cellforce_visit(void *vctx, int32_t i, int32_t j, const int8_t img[3
 }
 
 /* Forces straight from the cells, no stored list (the cell method of
- * Sec. 2.1): same enumeration as the half list with r_n = r_c. */
+ * Sec. 3.1): same enumeration as the half list with r_n = r_c. */
 int or_forces_cells(int64_t n, const double *x, const double *y, const double *z, double L,
                     int G, double rc, double ushift, double *fx, double *fy, double *fz,
                     double *ua, double *wa, double *out, const or_mix *mix)
@@ -553,7 +553,7 @@ int64_t or_neighbors_of_atom(int64_t n, const double *x, const double *y, const 
 }
 
 /* ------------------------------------------------------------------------ */
-/* The MD loop (Sec. 2.1, steps (a)-(e))                                     */
+/* The MD loop (Sec. 3.1, steps (a)-(e))                                     */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -821,8 +821,8 @@ int or_sim_run(or_sim *s, int64_t nsteps, double *trace)
     return rc;
 }
 
-/* Step (f) of the loop (Sec. 2.1), as used during the equilibration period
- * of Sec. 4: scale every velocity by one factor so that the kinetic
+/* Step (f) of the loop (Sec. 3.1), as used during the equilibration period
+ * of Sec. 5.1: scale every velocity by one factor so that the kinetic
  * temperature equals T.  With the centre of mass at rest the velocities carry
  * 3 (N - 1) degrees of freedom, so the target is sum v^2 = 3 (N - 1) T.
  * The sum is the plain sequential one.  Returns the factor (1 when there is

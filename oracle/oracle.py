@@ -387,7 +387,7 @@ class Sim:
 
     def equilibrate_run(self, nsteps: int, temperature: float, equil_steps: int = 500,
                         interval: int = 20) -> np.ndarray:
-        """``run`` with the equilibration of Sec. 4 folded in: after step k
+        """``run`` with the equilibration of Sec. 5.1 folded in: after step k
         (absolute count) with k <= equil_steps and k a multiple of interval,
         the velocities are adjusted to T.  Properties of step k in the trace
         are those of (e), before the adjustment."""
@@ -417,7 +417,7 @@ def block_means(trace: np.ndarray, n_atoms: int, first: int, last: int) -> dict:
     """Means over steps first..last (1-based, inclusive) of a trace that starts
     at step 1: per-atom kinetic, potential and total energy and virial, and
     the mean neighbour-list length per atom (twice the pairs per atom, the
-    quantity the paper tabulates as neighbours per atom).  Sec. 4 averages
+    quantity the paper tabulates as neighbours per atom).  Sec. 5.1 averages
     properties over blocks of 1000 steps."""
     rows = trace[first - 1:last]
     ke = rows[:, 0].mean() / n_atoms

@@ -1,9 +1,9 @@
 // md_ab.hip -- the Newton's-third-law A/B of the force phase.
 //
-// The paper drops Newton's third law on the GPU (Sec. 2.3): every atom keeps
+// The paper drops Newton's third law on the GPU (Sec. 3.3): every atom keeps
 // the full list of its neighbours and sums only its own force, so no two
 // threads ever write one location.  The CPU form it gives up keeps each pair
-// once and adds the reaction to the partner (Sec. 2.2).  These kernels put
+// once and adds the reaction to the partner (Sec. 3.2).  These kernels put
 // both forms side by side on gfx950 with one plain structure: a list over the
 // cell-sorted storage (entries are storage indices with the image code, no
 // LDS window), built full (every j != i) or half (j > i in storage order,

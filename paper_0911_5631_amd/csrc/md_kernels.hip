@@ -3,7 +3,7 @@
 // One time step k of every replica of an engine is two launches:
 //   k_sort  (b) when the displacement rule fires (always with the plain cell
 //           method): wrap, and a stable counting sort of the atoms by cell
-//           (Secs. 2.4, 2.5) -- cell_start from the occupancy counts, ranks
+//           (Secs. 3.4, 3.5) -- cell_start from the occupancy counts, ranks
 //           from the cell-layer rows, scatter into the other buffer variant.
 //           Replicas that do not rebuild leave at once.
 //   k_step  (b) the neighbour matrix W from the contiguous cell ranges of
@@ -163,7 +163,7 @@ __device__ __forceinline__ void latch_error(CtlDev &C, int bits, int64_t step) {
   atomicMin((unsigned long long *)&C.err_step, (unsigned long long)step);
 }
 
-// Cell and layer assignment of one atom (Secs. 2.2, 2.4): the atom's cell
+// Cell and layer assignment of one atom (Secs. 3.2, 3.4): the atom's cell
 // from its wrapped coordinates, a layer slot from the cell's occupancy
 // counter (atomic), the row entry, or the set's overflow list beyond hcap.
 __device__ __forceinline__ void bin_atom(SlotC &S, CtlDev &C, int set, int i, double x, double y,
@@ -288,7 +288,7 @@ __device__ __forceinline__ double ring_max(SlotC &S, int64_t e) {
   return wave_max(v);
 }
 
-// Rebuild decision for step k (Sec. 2.1): rebuilt when the accumulated sum
+// Rebuild decision for step k (Sec. 3.1): rebuilt when the accumulated sum
 // of vmax*dt exceeds delta/2.  disp after step k-1 is recomputed from the
 // committed disp after step k-2 and vmax of step k-1; *disp1 receives it.
 __device__ __forceinline__ bool rebuild_at(SlotC &S, const CtlDev &C, int64_t k,
@@ -351,8 +351,8 @@ __global__ void k_kick_end(Tables T) {
 // earlier tiles (counted while binning), cell_start of its cells follows
 // from a workgroup scan, and every atom goes to cell_start of its cell plus
 // its rank among the cell's atoms by current storage index -- the sequential
-// layer assignment of Sec. 2.4 read in cell order (Sec. 2.5), i.e. a stable
-// counting sort.  Positions are wrapped on the way (Sec. 2.1, step (b)).
+// layer assignment of Sec. 3.4 read in cell order (Sec. 3.5), i.e. a stable
+// counting sort.  Positions are wrapped on the way (Sec. 3.1, step (b)).
 // Workgroups depend on nobody.
 //   mode == MODE_STEP: step k = base + s + 1 of a run; replicas whose rule
 //   does not fire leave; v(k-1/2) is carried.
@@ -1562,7 +1562,7 @@ __global__ __launch_bounds__(TILE) void k_props(Tables T, int only) {
   }
 }
 
-// Step (f) during equilibration (Secs. 2.1 and 4): scale the velocities of a
+// Step (f) during equilibration (Secs. 3.1 and 5.1): scale the velocities of a
 // held clean state by one factor so that sum v^2 = 3 (N - 1) T (the centre of
 // mass is at rest, leaving 3 (N - 1) degrees of freedom), from the kinetic
 // energy k_props reduced just before.  The tile's kinetic-energy and max-v^2

@@ -145,9 +145,9 @@ def sp_256k() -> System:
 
 
 def system_s(shell: float = 0.6, seed: int = 6, n_edge: int = 48) -> System:
-    """The paper's system S (Sec. 4): simple cubic start of edge 48 (110 592
+    """The paper's system S (Secs. 5.1 and 5.3): simple cubic start of edge 48 (110 592
     atoms), rho 0.8, T 1, dt 0.005, FP32 forces; shell 0.6 unless given (the
-    Table 5 runs vary it).  2000 steps: the Sec. 4 equilibration (adjustment
+    Table 5 runs vary it).  2000 steps: the Sec. 5.1 equilibration (adjustment
     every 20 steps for 500) and the block of steps 1001-2000 of Table 4."""
     pos, L = sc_lattice(n_edge, 0.8)
     vel = random_velocities(len(pos), 1.0, seed)

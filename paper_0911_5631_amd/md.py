@@ -153,7 +153,7 @@ class System:
 
     def equilibrate_run(self, n_steps: int, temperature: float, equil_steps: int = 500,
                         interval: int = 20) -> None:
-        """md_step with the equilibration of Sec. 4 folded in: after every
+        """md_step with the equilibration of Sec. 5.1 folded in: after every
         step k (absolute count) with k <= equil_steps and k a multiple of
         interval, md_adjust_temp(temperature).  One synchronisation to read
         the step count; the rest is enqueued."""

@@ -1,4 +1,4 @@
-"""Equilibration (step (f) of the loop in Sec. 2.1, on the Sec. 4 schedule)
+"""Equilibration (step (f) of the loop in Sec. 3.1, on the Sec. 5.1 schedule)
 and block averages on the GPU, through the C ABI.
 
 Bar: the adjustment scales the held velocities by the factor the kinetic
@@ -156,7 +156,7 @@ def test_block_state_errors_and_reset():
 
 def test_system_s_reproduces_table4():
     """System S (simple cubic N_e = 48, rho 0.8, T 1, delta 0.6, dt 0.005) with
-    the Sec. 4 equilibration: <e_tot> and <e_kin> over steps 1001-2000
+    the Sec. 5.1 equilibration: <e_tot> and <e_kin> over steps 1001-2000
     against Table 4.  The last adjustment fixes e_kin, so e_tot keeps the
     potential energy of step 500, whose spread is the canonical fluctuation
     of u per atom: 0.011 at N = 8000 measured with the oracle, so 0.0030 at
@@ -187,7 +187,7 @@ def test_system_s_reproduces_table5(delta):
     and 15.96 for delta 0.4, 0.6, 0.8 (printed: 8.1, 12.0, 15.9), but one
     run's rebuild count (about 400-750) follows the maximum speed, an extreme
     value over the atoms; N_l within 1.  N_l is the largest cell occupancy,
-    a number that varies from sort to sort (Sec. 2.4), so it is read at the
+    a number that varies from sort to sort (Sec. 3.4), so it is read at the
     run's last sort: the oracle's equilibrated fluid gives 7-8 at delta 0.4
     and 11-12 at 0.8 (printed: 7 and 11), whereas the maximum over the whole
     run includes the simple cubic start with up to 8 sites in a cell."""
@@ -213,7 +213,7 @@ def test_system_s_reproduces_table5(delta):
 
 
 def test_system_s_energy_drift_over_1e5_steps():
-    """Table 4 over a long run: system S after the Sec. 4 equilibration, the
+    """Table 4 over a long run: system S after the Sec. 5.1 equilibration, the
     mean total energy per atom over the 1000 steps before N_step = 100 000
     against the same mean before 2 000.  The paper's FP32 run drifts by
     (2.3265371 - 2.3260603) / 2.326 = 2.0e-4 (its 'one part in 5000'); FP32

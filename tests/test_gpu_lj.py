@@ -1,5 +1,5 @@
 """Lennard-Jones with the longer cutoffs of the paper's LJ runs (r_c = 2.2,
-2.5, 3.0; rho 0.38, T 1.2, delta 0.8: Sec. 4, Tables 1 and 3): the same
+2.5, 3.0; rho 0.38, T 1.2, delta 0.8: Sec. 5.1, Tables 1 and 3): the same
 kernels without the soft-sphere shift, against the FP64 oracle.
 
 Bars as for the soft spheres: pair sets bit-exact; FP32 forces
@@ -71,7 +71,7 @@ def test_lj_pairs_bit_exact(rc, n_edge, seed):
 def test_lj_bins_bit_exact(rc, n_edge, seed):
     """Cells of 10-40 atoms: the sort ranks them cooperatively, and a cell
     tile is shared by several workgroups; the storage order must still be the
-    stable counting sort (Sec. 2.4 layers read in cell order, Sec. 2.5)."""
+    stable counting sort (Sec. 3.4 layers read in cell order, Sec. 3.5)."""
     pos, vel, L = lj_fluid(n_edge, seed)
     s = _system(pos, vel, L, r_cut=rc, shell=SHELL)
     G = O.cells_per_edge(L, rc + SHELL)
@@ -154,7 +154,7 @@ def test_lj_fp32_trajectory_matches_oracle():
 
 def test_lj_table1_system_counts():
     """LJ r_c = 3.0 at Table 1's N_e = 48 (110 592 atoms): N_c = 4096 exactly;
-    after the Sec. 4 equilibration the neighbour-list entries per atom,
+    after the Sec. 5.1 equilibration the neighbour-list entries per atom,
     quoted as typically 89 for the LJ runs, are 87.6 in the FP64 oracle at
     N_e = 16 and 24 (the tolerance, 2.5 %, covers that and the rounding of
     the quote); the layer count N_l (largest cell occupancy at a sort) is

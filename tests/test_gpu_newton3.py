@@ -1,6 +1,6 @@
 """Newton's-third-law A/B of the force phase (md_newton3_ab): the full list
-(Sec. 2.3, no reaction forces) and the half list with atomic reactions (the
-CPU form of Sec. 2.2) against the oracle and against each other.
+(Sec. 3.3, no reaction forces) and the half list with atomic reactions (the
+CPU form of Sec. 3.2) against the oracle and against each other.
 
 Bar: list sizes exact (full = 2 x half = 2 x the oracle's pair count);
 forces of both forms within the FP32 force bar of the other parity tests,

@@ -1,5 +1,5 @@
-"""Pins of the oracle's equilibration (step (f) of the loop in Sec. 2.1, the
-schedule of Sec. 4) and block averages against the equilibrated-fluid
+"""Pins of the oracle's equilibration (step (f) of the loop in Sec. 3.1, the
+schedule of Sec. 5.1) and block averages against the equilibrated-fluid
 physics the paper prints (Tables 4 and 5, tests/golden/paper_table4_table5.txt)
 and against invariants of a uniform velocity scaling.  CPU only."""
 import os
@@ -29,7 +29,7 @@ def _golden():
 
 
 def _system_s(n_edge, shell, seed):
-    # system S of Sec. 4 at a smaller edge: simple cubic start, rho 0.8, T 1
+    # system S of Sec. 5.1 at a smaller edge: simple cubic start, rho 0.8, T 1
     pos, L = I.sc_lattice(n_edge, 0.8)
     vel = I.random_velocities(len(pos), 1.0, seed)
     return pos, vel, L
@@ -129,7 +129,7 @@ def test_cell_counts_of_table5_rows():
 
 
 def test_energies_match_table4():
-    """<e_tot> and <e_kin> over steps 1001-2000 after the Sec. 4
+    """<e_tot> and <e_kin> over steps 1001-2000 after the Sec. 5.1
     equilibration (Table 4, N_step = 2000).  The last adjustment (step 500)
     fixes e_kin exactly, so e_tot keeps the potential energy of that one
     instant: its spread over seeds is the canonical fluctuation of u per atom,

@@ -1,5 +1,5 @@
 """Pins of the oracle's several-species pair model (the extension the paper
-names at the end of Sec. 2: per species pair epsilon, sigma, cutoff and
+names in Sec. 3.5: per species pair epsilon, sigma, cutoff and
 shift; Eq. (1) in the pair's units).  CPU only."""
 import math
 

@@ -35,7 +35,7 @@ def _golden_cell_rows():
 @pytest.mark.parametrize("row", _golden_cell_rows(), ids=lambda r: f"{r[0]}-{r[1]}-{r[2]}-{r[5]}")
 def test_cell_counts_match_paper_tables(row):
     src, pot, ne, rho, rc, delta, nc = row
-    L = ne / rho ** (1.0 / 3.0)           # Sec. 2.1: L = N_e / rho^(1/3)
+    L = ne / rho ** (1.0 / 3.0)           # Sec. 3.1: L = N_e / rho^(1/3)
     G = O.cells_per_edge(L, rc + delta, even=True)
     assert G ** 3 == nc
 
@@ -161,7 +161,7 @@ def test_wrap_half_open_and_exact():
 
 
 def test_cell_ids_closed_form():
-    # Sec. 2.1: c = ((c_z - 1) G + c_y - 1) G + c_x (1-based); 0-based here.
+    # Sec. 3.1: c = ((c_z - 1) G + c_y - 1) G + c_x (1-based); 0-based here.
     L, G = 9.0, 6
     w = L / G
     pos = np.array([[-L / 2 + 0.5 * w, -L / 2 + 1.5 * w, -L / 2 + 2.5 * w],
@@ -357,7 +357,7 @@ def test_cell_only_mode_matches_list_mode_trajectory():
 
 
 # ---------------------------------------------------------------------------
-# Lennard-Jones with the longer cutoffs of Sec. 4 (no shift)
+# Lennard-Jones with the longer cutoffs of Sec. 5.1 (no shift)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("rc", [2.2, 2.5, 3.0])
