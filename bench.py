@@ -1,12 +1,15 @@
 """Benchmark: soft-sphere MD throughput in atom-steps/s on one MI355X.
 
-Workload (default): N = 256 000 atoms (fcc 40^3 x 4), density 0.8, T = 1,
-truncated-shifted LJ at r_c = 2^(1/6), neighbour shell 0.4 rebuilt by the
-displacement rule, dt = 0.005, FP32 forces on FP64 positions/velocities.
-A "step" is one leapfrog time step of the whole system: (a) kick+drift,
-(b) wrap/bin/reorder/neighbour build when due, (c) forces, (d) kick,
-(e) properties and the rebuild decision.  Inputs are synthetic (seeded fcc
-start with random velocity directions) and resident in HBM before timing.
+Workload (default): the largest single system, N = 4 000 000 atoms (fcc
+100^3 x 4), density 0.8, T = 1, truncated-shifted LJ at r_c = 2^(1/6),
+neighbour shell 0.4 rebuilt by the displacement rule, dt = 0.005, FP32
+forces on FP64 positions/velocities.  A "step" is one leapfrog time step of
+the whole system: (a) kick+drift, (b) wrap/bin/reorder/neighbour build when
+due, (c) forces, (d) kick, (e) properties and the rebuild decision.  Inputs
+are synthetic (seeded fcc start with random velocity directions, melted for
+200 untimed steps so that the timed steps see the fluid's steady rebuild
+rate) and resident in HBM before timing; every replay graph is captured at
+creation.
 
 Prints ONE JSON line.  Besides the throughput it reports
   roofline      the step kernel k_step (forces, list build at rebuilds,
@@ -15,7 +18,12 @@ Prints ONE JSON line.  Besides the throughput it reports
                 duration, measured with HIP events around every launch on the
                 library's stream in a second region of the same length;
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample of
-                the same workload (one core).
+                the same workload (one core), with the host's CPU model;
+  batched       the replica workload (256 systems, N = 4 k^3, k ~ U{6..20},
+                5000 steps) in one batch, against the same systems stepped
+                one after another through the single-system path;
+  served        a Poisson trace of the served workload (k ~ U{6..50}, 1000 to
+                20 000 steps, 50 arrivals/s) through the serving loop.
 """
 from __future__ import annotations
 
@@ -77,23 +85,43 @@ def traffic_per_launch(n_atoms: int):
     return t.get("hbm_bytes_per_launch")
 
 
-def batched(n_replicas: int, steps: int, n_solo: int, solo_steps: int) -> dict:
+TUNE_CACHE = os.path.join(ROOT, "paper_0911_5631_amd", "tune_cache.json")
+
+
+def gpu_arch() -> str:
+    import torch
+    return getattr(torch.cuda.get_device_properties(0), "gcnArchName", "gfx950")
+
+
+def batched(n_replicas: int, steps: int, n_solo: int, solo_steps: int,
+            tune_cache: str) -> dict:
     """Replicas of uneven size (N = 4 k^3, k ~ U{6..20}, rho ~ U[0.7, 0.9],
-    T ~ U[0.8, 1.5]) advanced together in one batch (launch configuration
-    autotuned on the run itself) against the same systems run one after
-    another through the single-system path."""
+    T ~ U[0.8, 1.5]) advanced together in one batch, against the same
+    systems run one after another through the single-system path.  The
+    batch's launch configuration comes from the tuning cache (arch, batch,
+    atom-count bucket) or, without an entry, from the autotuner on the run
+    itself (its trial steps are part of the timed work).  The sequential
+    comparator creates and warms every solo system (upload, first sort,
+    graph capture) before its clock starts and times only its steps."""
     import torch
     from paper_0911_5631_amd import inputs as I
+    from paper_0911_5631_amd import tune as TU
     from paper_0911_5631_amd.md import Batch, System
-    from paper_0911_5631_amd.tune import autotune
     systems = I.replica_batch(n_replicas=n_replicas, steps=steps)
+    atoms = int(sum(s.n for s in systems))
     work = float(sum(s.n * s.steps for s in systems))
+    key = TU.cache_key(gpu_arch(), "batch", atoms)
     b = Batch(64 << 30, n_replicas, 64)
+    t_adm = time.perf_counter()
     for s in systems:
         b.admit(s.pos, s.vel, s.box, s.steps, shell=s.shell, dt=s.dt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tune = autotune(b, runs=1)
+    cfg = TU.apply_cached(b, tune_cache, key)
+    tuned = None
+    if cfg is None:
+        tuned = TU.autotune(b, runs=1, cache_path=tune_cache, key=key)
+        cfg = tuned["in_use"]
     done = 0
     while done < n_replicas:
         b.run()
@@ -102,23 +130,37 @@ def batched(n_replicas: int, steps: int, n_solo: int, solo_steps: int) -> dict:
             done += 1
     el = time.perf_counter() - t0
     b.close()
-    # one after another, each system alone (a sample of the same replicas)
-    solo_work = 0.0
-    t1 = time.perf_counter()
+    # one after another, each system alone (a sample of the same replicas):
+    # created and warmed first, then only md_step + the synchronising props
+    solo = []
     for s in systems[:n_solo]:
         sy = System(s.pos, s.vel, s.box, shell=s.shell, dt=s.dt)
+        sy.step(8)
+        sy.props()
+        solo.append((sy, s.n))
+    el_solo = 0.0
+    solo_work = 0.0
+    for sy, n in solo:
+        t1 = time.perf_counter()
         sy.step(solo_steps)
         sy.props()
+        el_solo += time.perf_counter() - t1
+        solo_work += n * solo_steps
         sy.close()
-        solo_work += s.n * solo_steps
-    el_solo = time.perf_counter() - t1
-    return {"replicas": n_replicas, "atoms": int(sum(s.n for s in systems)), "steps": steps,
-            "atom_steps_per_s": work / el, "seconds": el,
-            "sequential_atom_steps_per_s": solo_work / el_solo,
-            "sequential_sample": f"first {n_solo} replicas x {solo_steps} steps, each created, "
-                                 "stepped and read back alone",
-            "speedup_vs_sequential": (work / el) / (solo_work / el_solo),
-            "autotuned": tune["best"]}
+    rate = work / el
+    seq = solo_work / el_solo
+    out = {"replicas": n_replicas, "atoms": atoms, "steps": steps,
+           "atom_steps_per_s": rate, "seconds": el,
+           "admission_seconds": t0 - t_adm,
+           "sequential_atom_steps_per_s": seq,
+           "sequential_sample": f"first {n_solo} replicas x {solo_steps} steps, each alone, "
+                                "created and warmed before timing (md_step + props only)",
+           "speedup_vs_sequential": rate / seq,
+           "launch_config": cfg, "tune_key": key,
+           "tune_source": "cache" if tuned is None else "autotuned on this run"}
+    if tuned is not None:
+        out["tune_trials"] = tuned["trials"]
+    return out
 
 
 def served(n_requests: int, rate: float, k_hi: int, steps_lo: int, steps_hi: int,
@@ -132,7 +174,7 @@ def served(n_requests: int, rate: float, k_hi: int, steps_lo: int, steps_hi: int
     res = serve(reqs, int(budget_gb * (1 << 30)), max_slots=min(256, n_requests))
     out = {k: v for k, v in res.items() if k != "served"}
     out.update({"rate_per_s": rate, "k_range": [6, k_hi], "steps_range": [steps_lo, steps_hi],
-                "hbm_budget_gb": budget_gb})
+                "hbm_budget_gb": budget_gb, "requests": n_requests})
     return out
 
 
@@ -308,9 +350,26 @@ def cpu_baseline_replicas(systems, budget_s: float) -> dict:
         res = list(ex.map(_oracle_replica, jobs))
     rate = sum(a / el for a, el in res)
     return {"value": rate, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+            "host": host_info(),
             "sample": f"replicas 1..{cores} of the batch (N {min(s.n for s in sample)}.."
                       f"{max(s.n for s in sample)}), one oracle process per core, "
                       f"{budget_s:.0f} s each from their starts"}
+
+
+def host_info() -> dict:
+    """The host the oracle ran on: CPU model, logical CPUs, CPUs this process
+    may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
 
 
 def cpu_baseline(sys_in, budget_s: float):
@@ -361,20 +420,27 @@ def cpu_baseline(sys_in, budget_s: float):
     return {"value": n * steps / el, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"N={n}, steps 1..{steps} from the fcc start ({el:.1f} s, one thread, "
                       f"FP64, linked-list cells + 14-cell half list + Newton's third law)",
-            "parity": parity}
+            "host": host_info(), "parity": parity}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--melt", type=int, default=200,
+                    help="untimed steps from the fcc start before the warm-up (input "
+                         "preparation: the fluid's steady rebuild rate)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="launch-configuration cache to read (and to write when tuning)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample (0: skip)")
-    ap.add_argument("--workload", default="sp_256k",
+    ap.add_argument("--workload", default="sp_4m",
                     choices=["sp_256k", "sp_4m", "sp_33m", "sp_small", "batch", "served",
-                             "equil", "lj", "newton3", "mixture"],
-                    help="single system (default sp_256k); 'batch' / 'served' run only the full "
+                             "equil", "lj", "newton3", "mixture", "tune"],
+                    help="single system (default sp_4m); 'tune' autotunes the single-system "
+                         "workloads' launch configuration into the cache; "
+                         "'batch' / 'served' run only the full "
                          "batched-replica or served-stream workload and print its JSON line; "
                          "'equil' the paper's system S with equilibration and block averages; "
                          "'lj' the Lennard-Jones runs of Tables 1 and 3; 'newton3' the full- vs "
@@ -403,8 +469,24 @@ def main() -> int:
     from paper_0911_5631_amd.md import System
 
     torch.cuda.set_device(0)
+    if args.workload == "tune":
+        from paper_0911_5631_amd import tune as TU
+        out = {}
+        for make in (I.sp_256k, I.sp_4m):
+            wl = make()
+            s = System(wl.pos, wl.vel, wl.box, shell=wl.shell, dt=wl.dt, precision=wl.precision)
+            s.step(args.melt)
+            key = TU.cache_key(gpu_arch(), "single", wl.n)
+            r = TU.autotune_system(s, wl.n, cache_path=args.tune_cache, key=key)
+            out[wl.name] = {"key": key, "best": r["best"], "trials": r["trials"]}
+            s.close()
+            print(f"# tuned {wl.name}: {r['best']}", file=sys.stderr, flush=True)
+        print(json.dumps({"metric": "launch-configuration autotuning", "value": None,
+                          "unit": "atom-steps/s", "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": "tune"}, "tune": out}), flush=True)
+        return 0
     if args.workload == "batch":
-        r = batched(256, 5000, 32, 1000)
+        r = batched(256, 5000, 32, 1000, args.tune_cache)
         line = {"metric": "atom-steps/s, 256 batched replicas", "value": r["atom_steps_per_s"],
                 "unit": "atom-steps/s", "n_gpus": 1, "higher_is_better": True,
                 "data": "synthetic", "config": {"workload": "replica_batch_256"}, "batched": r}
@@ -472,6 +554,13 @@ def main() -> int:
     n = wl.n
     s = System(wl.pos, wl.vel, wl.box, shell=wl.shell, dt=wl.dt, precision=wl.precision)
     print(f"# created {wl.name}: N={n} L={wl.box:.4f}", file=sys.stderr, flush=True)
+    from paper_0911_5631_amd import tune as TU
+    launch = TU.apply_cached(s, args.tune_cache, TU.cache_key(gpu_arch(), "single", n))
+    # input preparation: the fcc start melts (its first rebuilds come late,
+    # while every atom still moves at the initial speed)
+    if args.melt > 0:
+        s.step(args.melt)
+        s.props()
     s.step(args.warmup)
     p0 = s.props()
     torch.cuda.synchronize()
@@ -521,7 +610,9 @@ def main() -> int:
         "data": "synthetic (seeded fcc start, random velocity directions)",
         "config": {"workload": wl.name, "n_atoms": n, "density": wl.rho,
                    "temperature": wl.temperature, "shell": wl.shell, "dt": wl.dt,
-                   "box": wl.box, "parallelism": "single-gpu"},
+                   "box": wl.box, "parallelism": "single-gpu",
+                   "start": f"fcc, melted {args.melt} untimed steps before the warm-up",
+                   "launch_config": launch or "library default"},
         "roofline": {"bound": "hbm", "kernel": "k_step", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": bytes_launch,
@@ -536,16 +627,18 @@ def main() -> int:
     }
     s.close()
     if not args.no_extras:
-        # the batched-replica and served-stream workloads, reduced in steps
-        # and requests so the default run stays within minutes (the full ones:
-        # --workload batch / --workload served)
-        out["batched"] = batched(256, 400, 32, 200)
+        # the replica workload at its full size (256 systems, 5000 steps) and
+        # the served workload's distribution in a trace of 64 requests, so the
+        # default run stays within minutes (256 requests: --workload served)
+        out["batched"] = batched(256, 5000, 32, 1000, args.tune_cache)
+        out["batched"]["single_system_atom_steps_per_s"] = value
         print(f"# batched: {out['batched']['atom_steps_per_s']:.4g} atom-steps/s "
               f"({out['batched']['speedup_vs_sequential']:.1f}x sequential)", file=sys.stderr,
               flush=True)
-        out["served"] = served(64, 200.0, 20, 200, 2000, 32.0)
+        out["served"] = served(64, 50.0, 50, 1000, 20000, 32.0)
         print(f"# served: p50 {out['served']['p50_latency_s']:.3f} s, p99 "
-              f"{out['served']['p99_latency_s']:.3f} s", file=sys.stderr, flush=True)
+              f"{out['served']['p99_latency_s']:.3f} s, GPU busy "
+              f"{out['served']['gpu_busy_fraction']:.3f}", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -135,6 +135,21 @@ typedef struct {
                                N_p / N_a; 0 in cell-list-only mode) */
 } md_block_t;
 
+/* Launch configuration (md_configure, md_batch_configure).  None of these
+ * changes the arithmetic or its order, so a trajectory is the same bit for
+ * bit under any of them; they only cut the same work differently.  In: 0
+ * asks for the library's choice.  Out: the values in use. */
+typedef struct {
+    int32_t steps_per_run; /* steps per captured graph replay, 1..64 (0: 64) */
+    int32_t grid;          /* workgroups per step-kernel launch, 1..65535 (0: one
+                              per 256-atom tile up to 2048) */
+    int32_t sort_grid;     /* workgroups per sort launch, 1..65535 (0: a single
+                              system at most 512, a batch 2048) */
+    int32_t sort_split;    /* workgroups sharing one 256-cell tile of the sort,
+                              1..32 (0: about 1024 atoms per workgroup for a
+                              single system, 1 for a batch) */
+} md_launch_t;
+
 typedef struct {
     void *(*alloc)(size_t bytes, void *ctx); /* device memory, >= 256-byte aligned */
     void (*free)(void *ptr, void *ctx);
@@ -289,6 +304,10 @@ md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms);
 md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
                         double *build_ms, double *force_ms, int64_t *n_entries);
 
+/* Launch configuration of later steps (see md_launch_t); the replay graphs
+ * are captured again.  *cfg gets the configuration in use.  Sync. */
+md_status md_configure(md_system *s, md_launch_t *cfg);
+
 /* Release the system and its device memory (synchronises its stream). */
 void md_destroy(md_system *s);
 
@@ -305,11 +324,10 @@ void md_destroy(md_system *s);
 md_status md_batch_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_run,
                           const md_allocator *a, void *hip_stream, md_batch **out);
 
-/* Launch configuration of later runs: steps replayed per md_batch_run
- * (1..64) and workgroups per kernel launch (0: 2048; tiles beyond the grid
- * are taken in further passes).  Neither changes any arithmetic or its
- * order, so trajectories stay bit-identical; used by the autotuner.  Sync. */
-md_status md_batch_configure(md_batch *b, int32_t steps_per_run, int32_t grid);
+/* Launch configuration of later runs (see md_launch_t): steps replayed per
+ * md_batch_run and the workgroups of the launches.  *cfg gets the
+ * configuration in use.  Used by the autotuner.  Sync. */
+md_status md_batch_configure(md_batch *b, md_launch_t *cfg);
 
 /* Admit a system that is to advance n_steps steps; evaluates its step 0
  * (as md_create).  MD_ERR_OOM if it does not fit the remaining budget,
@@ -335,6 +353,13 @@ md_status md_batch_release(md_batch *b, int32_t slot);
 
 /* Bytes of the budget in use, and admitted systems. */
 md_status md_batch_usage(md_batch *b, size_t *bytes, int32_t *n_systems);
+
+/* Progress of the admitted systems, for timing a batch by the work it did:
+ * *atom_steps = sum over admitted systems of N x completed steps,
+ * *n_running = systems with steps still to go and no error, *min_remaining =
+ * the fewest steps any of them still has to go (0 when none runs).  Sync. */
+md_status md_batch_progress(md_batch *b, int64_t *atom_steps, int32_t *n_running,
+                            int64_t *min_remaining);
 
 /* Release the batch and every admitted system. */
 void md_batch_destroy(md_batch *b);

@@ -28,9 +28,9 @@ EXPORTS = (
     "md_build_nebr", "md_forces", "md_step", "md_props", "md_get_state",
     "md_get_atom_energies", "md_set_state", "md_get_cells", "md_get_bins", "md_get_pairs",
     "md_adjust_temp", "md_block_begin", "md_block_end", "md_newton3_ab", "md_set_species",
-    "md_profile", "md_kernel_time", "md_destroy", "md_batch_create", "md_batch_admit",
+    "md_profile", "md_kernel_time", "md_configure", "md_destroy", "md_batch_create", "md_batch_admit",
     "md_batch_configure", "md_batch_run", "md_batch_poll", "md_batch_props", "md_batch_get_state",
-    "md_batch_release", "md_batch_usage", "md_batch_destroy",
+    "md_batch_release", "md_batch_usage", "md_batch_progress", "md_batch_destroy",
 )
 
 
@@ -59,6 +59,11 @@ class md_props_t(C.Structure):
                 ("n_pairs", C.c_int64), ("n_rebuilds", C.c_int64), ("step", C.c_int64),
                 ("max_nebr", C.c_int32), ("max_cell", C.c_int32), ("rebuild_due", C.c_int32),
                 ("cells_per_edge", C.c_int32)]
+
+
+class md_launch_t(C.Structure):
+    _fields_ = [("steps_per_run", C.c_int32), ("grid", C.c_int32), ("sort_grid", C.c_int32),
+                ("sort_split", C.c_int32)]
 
 
 class md_block_t(C.Structure):
@@ -142,7 +147,9 @@ def lib():
         L.md_batch_admit.restype = st
         L.md_batch_admit.argtypes = [_P, C.POINTER(md_params), _D, _D, C.c_int64, _I32]
         L.md_batch_configure.restype = st
-        L.md_batch_configure.argtypes = [_P, C.c_int32, C.c_int32]
+        L.md_batch_configure.argtypes = [_P, C.POINTER(md_launch_t)]
+        L.md_configure.restype = st
+        L.md_configure.argtypes = [_P, C.POINTER(md_launch_t)]
         L.md_batch_run.restype = st
         L.md_batch_run.argtypes = [_P]
         L.md_batch_poll.restype = st
@@ -155,6 +162,8 @@ def lib():
         L.md_batch_release.argtypes = [_P, C.c_int32]
         L.md_batch_usage.restype = st
         L.md_batch_usage.argtypes = [_P, C.POINTER(C.c_size_t), _I32]
+        L.md_batch_progress.restype = st
+        L.md_batch_progress.argtypes = [_P, _I64, _I32, _I64]
         L.md_batch_destroy.restype = None
         L.md_batch_destroy.argtypes = [_P]
         _lib = L

@@ -113,7 +113,8 @@ __global__ __launch_bounds__(TILE) void k_ab_forces(const double *__restrict__ x
     const double s = (dx * dx + dy * dy) + dz * dz;
     if (s < rc2) {
       const float sr = (float)s;
-      const float rri = __builtin_amdgcn_rcpf(sr);
+      const float r0 = __builtin_amdgcn_rcpf(sr);  // refined as the step kernel does
+      const float rri = __builtin_fmaf(r0, __builtin_fmaf(-sr, r0, 1.0f), r0);
       const float rri3 = rri * rri * rri;
       const float f = 48.f * rri3 * (rri3 - 0.5f) * rri;
       const float ax = f * (float)dx, ay = f * (float)dy, az = f * (float)dz;

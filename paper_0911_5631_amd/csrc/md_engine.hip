@@ -168,6 +168,10 @@ struct Engine {
   int32_t *h_tab = nullptr;     // pinned: hdr + tile tables
   size_t h_tab_cap = 0;
   int grid = 1, cgrid = 1;
+  // launch configuration asked for by md_configure / md_batch_configure (0:
+  // the library's choice from the sizes; see apply_launch)
+  int grid_req = 0, cgrid_req = 0, split_req = 0;
+  int split = 1;                // workgroups per cell tile of the sort in use
   std::map<int, hipGraphExec_t> graphs;
   bool sticky_hip = false;
   bool verbose = getenv("MD_VERBOSE") != nullptr;
@@ -460,6 +464,7 @@ md_status upload_tables(Engine *e) {
     const double occ = (double)g.n / (double)g.ncell;
     split = std::max(1, std::min(32, (int)std::ceil(occ * CTILE / 1024.0)));
   }
+  if (e->split_req > 0) split = e->split_req;
   hdr[HDR_SPLIT] = split;
   for (int s = 0; s < e->max_slots; ++s) {
     Replica *r = e->rep[s];
@@ -482,10 +487,19 @@ md_status upload_tables(Engine *e) {
                          hipMemcpyHostToDevice, e->work);
   if (err == hipSuccess) err = hipStreamSynchronize(e->work);
   if (err != hipSuccess) return e->fail("upload tables", err);
-  if (!e->batch) {
+  // workgroups per launch: a single system one per tile up to MAX_GRID (the
+  // sort at most SORT_GRID: its idle launches then cost less); a batch, whose
+  // tiles change with every admission, MAX_GRID for both
+  if (e->batch) {
+    e->grid = MAX_GRID;
+    e->cgrid = MAX_GRID;
+  } else {
     e->grid = std::max(1, std::min(nt, MAX_GRID));
     e->cgrid = std::max(1, std::min(nct * split, SORT_GRID));
   }
+  if (e->grid_req > 0) e->grid = e->grid_req;
+  if (e->cgrid_req > 0) e->cgrid = e->cgrid_req;
+  e->split = split;
   return MD_OK;
 }
 
@@ -652,14 +666,18 @@ md_status repair_cells(Engine *e, int s) {
   Replica *r = e->rep[s];
   CtlDev &c = e->h_ctl[s];
   const int hcap = std::max(2 * r->g.hcap, r->g.hcap + 16);
+  const size_t grow = h_bytes(r->g, hcap) - h_bytes(r->g, r->g.hcap);
+  // a batch keeps its systems within the memory budget: a system whose rows
+  // cannot grow inside it keeps its error (reported for that slot alone)
+  if (e->batch && e->used + grow > e->budget) return MD_ERR_OOM;
   void *h = e->dmalloc(h_bytes(r->g, hcap));
   if (!h) return MD_ERR_CELL_OVERFLOW;
   hipError_t err = hipMemsetAsync(h, 0, h_bytes(r->g, hcap), e->work);
   if (err == hipSuccess) err = hipStreamSynchronize(e->work);
   if (err != hipSuccess) return e->fail("regrow", err);
   e->dfree(r->hmat);
-  r->bytes += h_bytes(r->g, hcap) - h_bytes(r->g, r->g.hcap);
-  e->used += h_bytes(r->g, hcap) - h_bytes(r->g, r->g.hcap);
+  r->bytes += grow;
+  e->used += grow;
   r->hmat = h;
   r->g.hcap = hcap;
   describe(r);
@@ -694,6 +712,8 @@ hipGraphExec_t step_graph(Engine *e, int k) {
   err = hipStreamEndCapture(e->work, &g);
   if (err == hipSuccess) err = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
+  // the executable graph goes to the device now, not at its first launch
+  if (err == hipSuccess) err = hipGraphUpload(x, e->work);
   if (err != hipSuccess) {
     e->fail("graph capture", err);
     return nullptr;
@@ -715,6 +735,16 @@ md_status prof_collect(Engine *e, int set) {
   e->prof_launches += k;
   e->prof_pending[set] = 0;
   return MD_OK;
+}
+
+// Capture every replay graph a run of a single system can use (K =
+// steps_per_run and its repeated halvings, plain kernels), so that no
+// md_step pays for a capture.
+md_status prepare_graphs(Engine *e) {
+  for (int k = e->steps_per_run; k >= 1; k >>= 1)
+    if (!step_graph(e, k)) return MD_ERR_HIP;
+  hipError_t err = hipStreamSynchronize(e->work);
+  return err == hipSuccess ? MD_OK : e->fail("graph upload", err);
 }
 
 // K steps of every running replica, then the counter update.
@@ -743,11 +773,11 @@ md_status replay(Engine *e, int k) {
 }
 
 // Advance a single system from absolute step `from` to `to` in replays of
-// GRAPH_CHUNK steps and a power-of-two decomposition of the rest.
+// steps_per_run steps and a halving decomposition of the rest.
 md_status run_steps(Engine *e, int64_t from, int64_t to) {
   int64_t pos = from;
   while (pos < to) {
-    int k = GRAPH_CHUNK;
+    int k = e->steps_per_run;
     while (k > to - pos) k >>= 1;
     md_status st = replay(e, k);
     if (st != MD_OK) return st;
@@ -766,7 +796,9 @@ md_status settle(Engine *e) {
     for (int s = 0; s < e->max_slots; ++s) {
       if (!e->rep[s]) continue;
       if (e->h_ctl[s].err != ERR_CELL) continue;
-      if ((st = repair_cells(e, s)) != MD_OK) return st;
+      st = repair_cells(e, s);
+      if (st == MD_ERR_OOM && e->batch) continue;  // over budget: the slot keeps its error
+      if (st != MD_OK) return st;
       repaired = true;
       const CtlDev &c = e->h_ctl[s];
       if (!e->batch && c.target > c.done) {
@@ -1017,6 +1049,37 @@ md_status upload_species(Engine *e, Replica *r, int v) {
   return err == hipSuccess ? MD_OK : e->fail("upload species", err);
 }
 
+// Apply a launch configuration (md_configure / md_batch_configure): the
+// knobs change no arithmetic and no order of it, only how the work is cut
+// into workgroups and graph replays.  Fields are written back with the
+// values in use.
+md_status configure(Engine *e, md_launch_t *cfg) {
+  if (!cfg) return MD_ERR_INVALID_ARG;
+  if (cfg->steps_per_run < 0 || cfg->steps_per_run > GRAPH_CHUNK || cfg->grid < 0 ||
+      cfg->grid > 65535 || cfg->sort_grid < 0 || cfg->sort_grid > 65535 ||
+      cfg->sort_split < 0 || cfg->sort_split > 32)
+    return MD_ERR_INVALID_ARG;
+  if (e->sticky_hip) return MD_ERR_HIP;
+  hipError_t err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("configure", err);
+  const int spr = cfg->steps_per_run > 0 ? cfg->steps_per_run : GRAPH_CHUNK;
+  // captured graphs bake the grids and replay lengths in
+  for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+  e->graphs.clear();
+  e->steps_per_run = spr;
+  e->grid_req = cfg->grid;
+  e->cgrid_req = cfg->sort_grid;
+  e->split_req = cfg->sort_split;
+  md_status st = upload_tables(e);
+  if (st == MD_OK && !e->batch) st = prepare_graphs(e);
+  if (st != MD_OK) return st;
+  cfg->steps_per_run = e->steps_per_run;
+  cfg->grid = e->grid;
+  cfg->sort_grid = e->cgrid;
+  cfg->sort_split = e->split;
+  return MD_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1090,6 +1153,7 @@ md_status md_create(const md_params *p, const double *pos, const double *vel,
     }
     break;
   }
+  if (st == MD_OK) st = prepare_graphs(e);
   if (st == MD_OK) st = e->leave();
   if (st != MD_OK) {
     engine_free(e);
@@ -1478,6 +1542,12 @@ md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms) {
   return MD_OK;
 }
 
+md_status md_configure(md_system *s, md_launch_t *cfg) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  return configure(s->e, cfg);
+}
+
 void md_destroy(md_system *s) {
   if (!s) return;
   engine_free(s->e);
@@ -1497,8 +1567,6 @@ md_status md_batch_create(size_t hbm_budget, int32_t max_slots, int32_t steps_pe
   e->batch = true;
   e->budget = hbm_budget;
   e->steps_per_run = steps_per_run;
-  e->grid = MAX_GRID;
-  e->cgrid = MAX_GRID;
   md_status st = engine_init(e, max_slots, a, hip_stream);
   if (st == MD_OK) st = upload_tables(e);
   if (st != MD_OK) {
@@ -1514,23 +1582,9 @@ md_status md_batch_create(size_t hbm_budget, int32_t max_slots, int32_t steps_pe
   return MD_OK;
 }
 
-md_status md_batch_configure(md_batch *b, int32_t steps_per_run, int32_t grid) {
-  if (!b || !b->e || steps_per_run <= 0 || steps_per_run > GRAPH_CHUNK || grid < 0 ||
-      grid > 65535)
-    return MD_ERR_INVALID_ARG;
-  Engine *e = b->e;
-  if (e->sticky_hip) return MD_ERR_HIP;
-  hipError_t err = hipStreamSynchronize(e->work);
-  if (err != hipSuccess) return e->fail("configure", err);
-  const int g = grid > 0 ? grid : MAX_GRID;
-  if (g != e->grid) {
-    // captured graphs bake the grid in
-    for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
-    e->graphs.clear();
-  }
-  e->grid = e->cgrid = g;
-  e->steps_per_run = steps_per_run;
-  return MD_OK;
+md_status md_batch_configure(md_batch *b, md_launch_t *cfg) {
+  if (!b || !b->e) return MD_ERR_INVALID_ARG;
+  return configure(b->e, cfg);
 }
 
 md_status md_batch_admit(md_batch *b, const md_params *p, const double *pos, const double *vel,
@@ -1666,6 +1720,31 @@ md_status md_batch_usage(md_batch *b, size_t *bytes, int32_t *n_systems) {
   for (Replica *r : b->e->rep) k += r != nullptr;
   *bytes = b->e->used;
   *n_systems = k;
+  return MD_OK;
+}
+
+md_status md_batch_progress(md_batch *b, int64_t *atom_steps, int32_t *n_running,
+                            int64_t *min_remaining) {
+  if (!b || !b->e || !atom_steps || !n_running || !min_remaining) return MD_ERR_INVALID_ARG;
+  Engine *e = b->e;
+  if (e->sticky_hip) return MD_ERR_HIP;
+  md_status st = read_ctl(e);
+  if (st != MD_OK) return st;
+  int64_t work = 0, rem = 0;
+  int32_t running = 0;
+  for (int s = 0; s < e->max_slots; ++s) {
+    const Replica *r = e->rep[s];
+    if (!r) continue;
+    const CtlDev &c = e->h_ctl[s];
+    work += r->g.n * c.done;
+    if (c.err == 0 && c.done < c.target) {
+      rem = running == 0 ? c.target - c.done : std::min(rem, c.target - c.done);
+      ++running;
+    }
+  }
+  *atom_steps = work;
+  *n_running = running;
+  *min_remaining = rem;
   return MD_OK;
 }
 

@@ -600,12 +600,20 @@ struct Acc {
   R fx, fy, fz, u, w;
 };
 
-__device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
+// FP32 1/s: the hardware reciprocal (within 1 ulp) refined by one Newton step
+// (two explicit FMAs), which brings it to about half an ulp.  The refinement
+// matters where every pair has the same separation (a lattice): a reciprocal
+// 1 ulp off then shifts every pair's virial term by ~2e-6 relative through
+// the cancellation in r^-6 - 1/2, and the shift does not average out.
+__device__ __forceinline__ float recip(float s) {
+  const float r = __builtin_amdgcn_rcpf(s);
+  return __builtin_fmaf(r, __builtin_fmaf(-s, r, 1.0f), r);
+}
 __device__ __forceinline__ double recip(double s) { return 1.0 / s; }
 
 // Pair force and energy of Eq. (1) with the soft-sphere shift: for r^2 = s,
 // f = 48 r^-8 (r^-6 - 1/2) (force on i is f d), u = 4 r^-6 (r^-6 - 1) + shift.
-// FP32 uses the hardware reciprocal (1 ulp).
+// FP32 uses the refined hardware reciprocal above.
 // The energy and virial terms are summed only when ENERGY is set (a
 // wave-uniform flag: the steps whose per-atom sums somebody reads); the
 // force arithmetic is the same either way.

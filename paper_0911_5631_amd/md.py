@@ -92,6 +92,10 @@ def _props_dict(p: L.md_props_t) -> Dict[str, float]:
     return {name: getattr(p, name) for name, _ in L.md_props_t._fields_}
 
 
+def _launch_dict(cfg: L.md_launch_t) -> Dict[str, int]:
+    return {name: getattr(cfg, name) for name, _ in L.md_launch_t._fields_}
+
+
 class System:
     """One periodic soft-sphere system resident on the GPU (md_create)."""
 
@@ -242,6 +246,14 @@ class System:
         check(lib().md_kernel_time(self._h, C.byref(k), C.byref(ms)), "md_kernel_time")
         return k.value, ms.value
 
+    def configure(self, steps_per_run: int = 0, grid: int = 0, sort_grid: int = 0,
+                  sort_split: int = 0) -> Dict[str, int]:
+        """Launch configuration of later steps (changes no arithmetic); 0 asks
+        for the library's choice.  Returns the configuration in use."""
+        cfg = L.md_launch_t(int(steps_per_run), int(grid), int(sort_grid), int(sort_split))
+        check(lib().md_configure(self._h, C.byref(cfg)), "md_configure")
+        return _launch_dict(cfg)
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().md_destroy(self._h)
@@ -297,11 +309,14 @@ class Batch:
                 return None
             raise
 
-    def configure(self, steps_per_run: int, grid: int = 0) -> None:
-        """Launch configuration of later runs (changes no arithmetic)."""
-        check(lib().md_batch_configure(self._h, int(steps_per_run), int(grid)),
-              "md_batch_configure")
-        self.steps_per_run = int(steps_per_run)
+    def configure(self, steps_per_run: int = 0, grid: int = 0, sort_grid: int = 0,
+                  sort_split: int = 0) -> Dict[str, int]:
+        """Launch configuration of later runs (changes no arithmetic); 0 asks
+        for the library's choice.  Returns the configuration in use."""
+        cfg = L.md_launch_t(int(steps_per_run), int(grid), int(sort_grid), int(sort_split))
+        check(lib().md_batch_configure(self._h, C.byref(cfg)), "md_batch_configure")
+        self.steps_per_run = cfg.steps_per_run
+        return _launch_dict(cfg)
 
     def run(self) -> None:
         check(lib().md_batch_run(self._h), "md_batch_run")
@@ -336,6 +351,16 @@ class Batch:
         k = C.c_int32()
         check(lib().md_batch_usage(self._h, C.byref(b), C.byref(k)), "md_batch_usage")
         return b.value, k.value
+
+    def progress(self) -> Tuple[int, int, int]:
+        """(atom-steps completed by the admitted systems, systems still
+        running, fewest steps any running system still has to go)."""
+        a = C.c_int64()
+        k = C.c_int32()
+        r = C.c_int64()
+        check(lib().md_batch_progress(self._h, C.byref(a), C.byref(k), C.byref(r)),
+              "md_batch_progress")
+        return a.value, k.value, r.value
 
     def close(self) -> None:
         if getattr(self, "_h", None):

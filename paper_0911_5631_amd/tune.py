@@ -1,41 +1,162 @@
-"""Launch-configuration autotuner for batched replicas.
+"""Launch-configuration autotuner for batches and single systems.
 
-The tunables are the ones that change neither the arithmetic nor its order,
-so every system's trajectory stays bit-identical whatever is chosen: the
-number of steps replayed per run (the length of the captured graph, which
-amortises the per-run kick and host round trip) and the workgroups per kernel
-launch (tiles beyond the grid are taken in further passes of the same
-workgroups).  Each candidate is timed on the batch's own admitted mix with
-real runs -- the steps count toward the systems' targets -- and the fastest
-per step is kept.
+The knobs are the ones that change neither the arithmetic nor its order, so
+every system's trajectory stays bit-identical whatever is chosen:
+
+  steps_per_run  length of the captured replay graph (amortises the per-run
+                 kick and host round trip);
+  grid           workgroups per step-kernel launch (tiles beyond the grid are
+                 taken in further passes of the same workgroups);
+  sort_grid      workgroups per sort launch;
+  sort_split     workgroups sharing one 256-cell tile of the sort.
+
+A batch is tuned on its own admitted mix with real runs (the steps count
+toward the systems' targets).  A trial is scored by the atom-steps the batch
+actually advanced per second, read from the device step counters before and
+after it; a trial during which a system finished or was admitted (the work
+per step changed) is discarded, and no trial is started that could finish a
+system.  Results are kept in a JSON cache keyed by GPU architecture, kind
+(batch or single system) and atom-count bucket.
 """
 from __future__ import annotations
 
+import json
+import math
+import os
 import time
-from typing import Dict, Iterable, List, Sequence, Tuple
+from typing import Dict, Iterable, List, Mapping, Optional
 
-DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = (
-    (16, 2048), (32, 2048), (64, 2048), (64, 1024), (64, 4096), (64, 8192))
+KNOBS = ("steps_per_run", "grid", "sort_grid", "sort_split")
+
+DEFAULT_CANDIDATES = (
+    {"steps_per_run": 16, "grid": 2048, "sort_grid": 2048, "sort_split": 1},
+    {"steps_per_run": 32, "grid": 2048, "sort_grid": 2048, "sort_split": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 2048, "sort_split": 1},
+    {"steps_per_run": 64, "grid": 1024, "sort_grid": 2048, "sort_split": 1},
+    {"steps_per_run": 64, "grid": 4096, "sort_grid": 2048, "sort_split": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 1024, "sort_split": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 4096, "sort_split": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 2048, "sort_split": 2},
+)
+
+SINGLE_CANDIDATES = (
+    {"steps_per_run": 64, "grid": 0, "sort_grid": 0, "sort_split": 0},
+    {"steps_per_run": 64, "grid": 1024, "sort_grid": 0, "sort_split": 0},
+    {"steps_per_run": 64, "grid": 4096, "sort_grid": 0, "sort_split": 0},
+    {"steps_per_run": 64, "grid": 0, "sort_grid": 256, "sort_split": 0},
+    {"steps_per_run": 64, "grid": 0, "sort_grid": 1024, "sort_split": 0},
+    {"steps_per_run": 32, "grid": 0, "sort_grid": 0, "sort_split": 0},
+)
 
 
-def autotune(batch, candidates: Iterable[Sequence[int]] = DEFAULT_CANDIDATES,
-             runs: int = 2) -> Dict:
-    """Time ``runs`` runs of ``batch`` per (steps_per_run, grid) candidate,
-    after one untimed run that captures the candidate's graph; configure the
-    batch with the fastest (seconds per step) and return the timings.
-    ``batch.poll()`` synchronises, so each timing covers the device work."""
+def _cfg(c: Mapping) -> Dict[str, int]:
+    return {k: int(c.get(k, 0)) for k in KNOBS}
+
+
+def size_bucket(n_atoms: int) -> int:
+    """Atom-count bucket: floor(log2 N) (systems within a factor of two share
+    a tuned configuration)."""
+    return int(math.floor(math.log2(max(int(n_atoms), 1))))
+
+
+def cache_key(arch: str, kind: str, n_atoms: int) -> str:
+    return f"{arch.split(':')[0]}/{kind}/{size_bucket(n_atoms)}"
+
+
+def load_cache(path: Optional[str]) -> Dict:
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def store(path: Optional[str], key: str, entry: Dict) -> None:
+    if not path:
+        return
+    cache = load_cache(path)
+    cache[key] = entry
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune(batch, candidates: Iterable[Mapping] = DEFAULT_CANDIDATES, runs: int = 2,
+             cache_path: Optional[str] = None, key: Optional[str] = None,
+             clock=None) -> Dict:
+    """Time ``runs`` runs of ``batch`` per candidate (after one untimed run
+    that captures the candidate's graph), score each by atom-steps advanced
+    per second, configure the batch with the best and return the trials.
+
+    ``batch`` offers configure(**knobs), run(), poll() (synchronises) and
+    progress() -> (atom-steps done, systems running, fewest steps left)."""
+    clock = clock or time.perf_counter
     trials: List[Dict] = []
-    for spr, grid in candidates:
-        batch.configure(int(spr), int(grid))
-        batch.run()
+    _, running, left = batch.progress()
+    budget = left - 1          # steps every running system can still take safely
+    for cand in candidates:
+        c = _cfg(cand)
+        spr = c["steps_per_run"] or 64
+        if running == 0 or (1 + runs) * spr > budget:
+            trials.append({**c, "skipped": "a trial could finish a system"})
+            continue
+        batch.configure(**c)
+        batch.run()            # captures this configuration's graph
         batch.poll()
-        t0 = time.perf_counter()
+        a0, k0, _ = batch.progress()
+        t0 = clock()
         for _ in range(runs):
             batch.run()
         batch.poll()
-        el = time.perf_counter() - t0
-        trials.append({"steps_per_run": int(spr), "grid": int(grid),
-                       "s_per_step": el / (runs * int(spr))})
-    best = min(trials, key=lambda t: t["s_per_step"])
-    batch.configure(best["steps_per_run"], best["grid"])
-    return {"best": best, "trials": trials}
+        el = clock() - t0
+        a1, k1, left1 = batch.progress()
+        budget -= (1 + runs) * spr
+        if k1 != k0:
+            trials.append({**c, "skipped": "the mix changed during the trial"})
+            continue
+        trials.append({**c, "atom_steps_per_s": (a1 - a0) / el if el > 0 else 0.0,
+                       "seconds": el})
+    scored = [t for t in trials if "atom_steps_per_s" in t]
+    if not scored:
+        return {"best": None, "trials": trials}
+    best = max(scored, key=lambda t: t["atom_steps_per_s"])
+    used = batch.configure(**{k: best[k] for k in KNOBS})
+    if key:
+        store(cache_path, key, {"config": {k: best[k] for k in KNOBS},
+                                "atom_steps_per_s": best["atom_steps_per_s"]})
+    return {"best": best, "in_use": used, "trials": trials}
+
+
+def autotune_system(system, n_atoms: int, candidates: Iterable[Mapping] = SINGLE_CANDIDATES,
+                    steps: int = 256, cache_path: Optional[str] = None,
+                    key: Optional[str] = None, clock=None) -> Dict:
+    """The same for one system: each candidate advances it ``steps`` real
+    steps (after one untimed replay that warms the new graphs), timed to the
+    synchronising props() call; the fastest is kept."""
+    clock = clock or time.perf_counter
+    trials: List[Dict] = []
+    for cand in candidates:
+        c = _cfg(cand)
+        system.configure(**c)
+        system.step(c["steps_per_run"] or 64)
+        system.props()
+        t0 = clock()
+        system.step(steps)
+        system.props()
+        el = clock() - t0
+        trials.append({**c, "atom_steps_per_s": n_atoms * steps / el if el > 0 else 0.0})
+    best = max(trials, key=lambda t: t["atom_steps_per_s"])
+    used = system.configure(**{k: best[k] for k in KNOBS})
+    if key:
+        store(cache_path, key, {"config": {k: best[k] for k in KNOBS},
+                                "atom_steps_per_s": best["atom_steps_per_s"]})
+    return {"best": best, "in_use": used, "trials": trials}
+
+
+def apply_cached(target, path: Optional[str], key: str) -> Optional[Dict[str, int]]:
+    """Configure ``target`` (a System or Batch) from the cache entry ``key``,
+    if there is one; returns the configuration in use, else None."""
+    entry = load_cache(path).get(key)
+    if not entry:
+        return None
+    return target.configure(**entry["config"])

@@ -40,8 +40,14 @@ def test_autotuned_batch_equals_solo():
     slot_of = {}
     for k, s in enumerate(systems):
         slot_of[b.admit(s.pos, s.vel, s.box, s.steps, shell=s.shell)] = k
-    res = autotune(b, candidates=((8, 64), (16, 512), (32, 2048), (64, 96)), runs=1)
+    cands = ({"steps_per_run": 8, "grid": 64, "sort_grid": 96, "sort_split": 1},
+             {"steps_per_run": 16, "grid": 512, "sort_grid": 2048, "sort_split": 2},
+             {"steps_per_run": 32, "grid": 2048, "sort_grid": 64, "sort_split": 3},
+             {"steps_per_run": 64, "grid": 96, "sort_grid": 512, "sort_split": 1})
+    res = autotune(b, candidates=cands, runs=1)
     assert res["best"] in res["trials"] and len(res["trials"]) == 4
+    assert all("atom_steps_per_s" in t for t in res["trials"])
+    assert res["in_use"] == {k: res["best"][k] for k in res["in_use"]}
     out = {}
     for _ in range(100):
         if len(out) == len(systems):

@@ -1,13 +1,19 @@
 """Parity at the workloads' full sizes, in the launch configuration bench.py
 times, and at the degenerate edges.
 
-At N = 256 000 and 4 000 000 the oracle cannot evaluate the whole system in
-seconds, so sampled atoms are checked one by one: the oracle's brute-force
-per-atom force and neighbour set (every atom, minimum image, same expression
-order) against the GPU's forces and neighbour-matrix rows.  Properties that
-hold at any size (momentum, symmetry of the pair set) are checked for all
-atoms.  Bars as in test_gpu_parity: forces max_i |dF_i| / max(|F_i|, F_rms)
-<= 1e-5; neighbour sets bit-exact.
+At N = 256 000 and 4 000 000 the oracle evaluates the whole system in
+seconds, so everything is compared completely on identical positions (the
+workload's fcc start jittered and stored in a shuffled order, so the sort
+moves every atom): cell ids, storage order and cell_start bit for bit, the
+complete neighbour-pair set bit for bit, every atom's force, the total
+potential energy and virial.  The sort inside a step is checked bit for bit
+at 4 x 10^6 atoms in FP64 against a stable sort, by the oracle's cells at its
+first rebuild, of the creation order.  Trajectories of the workloads' own
+fcc starts through graph replays with rebuilds are compared with the
+oracle's.  Bars as in test_gpu_parity: forces max_i |dF_i| / max(|F_i|,
+F_rms) <= 1e-5; PE and virial per atom |d(X/N)| <= 1e-6 max(|X/N|, 1);
+integer results bit-exact.  Only the 33.5 M-atom system (the 25-bit storage
+index limit) is checked on sampled atoms, against the oracle's per-atom sums.
 """
 import math
 
@@ -21,6 +27,7 @@ pytestmark = pytest.mark.gpu
 
 RC = 2.0 ** (1.0 / 6.0)
 FORCE_TOL = 1e-5
+ENERGY_TOL = 1e-6
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -35,6 +42,19 @@ def _gpu():
 def _system(*args, **kw):
     from paper_0911_5631_amd.md import System
     return System(*args, **kw)
+
+
+def force_error(f, ref):
+    scale = np.maximum(np.linalg.norm(ref, axis=1), math.sqrt((ref ** 2).sum(1).mean()))
+    return float((np.linalg.norm(f - ref, axis=1) / scale).max())
+
+
+def per_atom_error(x, ref, n):
+    return abs(x - ref) / n, ENERGY_TOL * max(abs(ref) / n, 1.0)
+
+
+def min_image(d, L):
+    return d - L * np.round(d / L)
 
 
 def _check_sampled_forces(pos, force, L, idx):
@@ -59,40 +79,126 @@ def _check_sampled_neighbours(s, pos, L, rn, idx):
     return pi, pj
 
 
-@pytest.mark.parametrize("make,steps,n_sample", [(I.sp_256k, 25, 256), (I.sp_4m, 30, 48)],
-                         ids=["sp_256k", "sp_4m"])
-def test_full_size_sampled_parity(make, steps, n_sample):
+def _fluid_start(wl, seed):
+    """The workload's fcc start jittered by up to 0.1 per coordinate (every
+    pair still farther apart than 0.85), stored in a shuffled order, with
+    some atoms moved one box length out of the region (wrapped at creation)."""
+    pos = I.jitter(wl.pos, wl.box, 0.1, seed)
+    pos, vel = I.shuffled(pos, wl.vel, seed + 1)
+    pos[::97, 0] += wl.box
+    pos[5::89, 2] -= wl.box
+    return pos, vel
+
+
+@pytest.mark.parametrize("make", [I.sp_256k, I.sp_4m], ids=["sp_256k", "sp_4m"])
+def test_full_size_complete_parity(make):
+    wl = make()
+    n, L = wl.n, wl.box
+    rn = RC + wl.shell
+    pos, vel = _fluid_start(wl, 31)
+    s = _system(pos, vel, L, shell=wl.shell, dt=wl.dt, precision=wl.precision)
+    G = O.cells_per_edge(L, rn)
+    assert s.props()["cells_per_edge"] == G
+    wrapped = O.wrap(pos, L)
+    p, _, f, step = s.get_state()
+    assert step == 0 and np.array_equal(p, wrapped)
+    # binning: cells, storage order, cell_start (a single system's sort
+    # walks several 256-cell tiles per workgroup at these sizes)
+    ref_cell = O.cell_ids(wrapped, L, G)
+    assert np.array_equal(s.cells(), ref_cell)
+    _, order, cs, _ = O.layers_reorder(ref_cell, G)
+    got_order, got_cs = s.bins()
+    assert np.array_equal(got_cs, cs)
+    assert np.array_equal(got_order, order)
+    del ref_cell, order, cs, got_order, got_cs
+    # the complete neighbour-pair set
+    rpi, rpj, rimg = O.pairs_cells(wrapped, L, G, rn)
+    pi, pj = s.pairs()
+    assert len(pi) == 2 * len(rpi) and bool(np.all(pi != pj))
+    assert np.array_equal(O.pair_set(pi, pj), O.pair_set(rpi, rpj))
+    assert s.props()["n_pairs"] == len(rpi)
+    del pi, pj
+    # every atom's force, total PE and virial, per-atom energies
+    ref = O.forces_pairs(wrapped, L, rpi, rpj, rimg)
+    assert force_error(f, ref.force) <= FORCE_TOL
+    pr = s.props()
+    e, bar = per_atom_error(pr["pe"], ref.pe, n)
+    assert e <= bar, (e, bar)
+    e, bar = per_atom_error(pr["virial"], ref.virial, n)
+    assert e <= bar, (e, bar)
+    u, w = s.atom_energies()
+    assert np.abs(u - ref.u_atom).max() <= 1e-5 * max(np.abs(ref.u_atom).max(), 1.0)
+    assert np.abs(w - ref.w_atom).max() <= 1e-5 * max(np.abs(ref.w_atom).max(), 1.0)
+    s.close()
+
+
+def test_step_sort_bit_exact_at_4m():
+    """FP64, the 4 x 10^6 fcc start: after the first rebuild inside md_step,
+    storage order and cell_start are the stable sort, by the cells of the
+    oracle's positions at its first rebuild, of the creation order; the pair
+    set built there is the oracle's."""
+    wl = I.sp_4m()
+    n, L = wl.n, wl.box
+    rn = RC + wl.shell
+    G = O.cells_per_edge(L, rn)
+    sim = O.Sim(wl.pos, wl.vel, L, shell=wl.shell, dt=wl.dt)
+    k1 = 0
+    while True:
+        k1 += 1
+        tr = sim.run(1)
+        if tr[0, 5]:
+            break
+        assert k1 < 200
+    r1, _, _, _ = sim.state()
+    _, order0, _, _ = O.layers_reorder(O.cell_ids(O.wrap(wl.pos, L), L, G), G)
+    cells1 = O.cell_ids(r1, L, G)
+    expect = order0[np.argsort(cells1[order0], kind="stable")]
+    _, _, cs1, _ = O.layers_reorder(cells1, G)
+    s = _system(wl.pos, wl.vel, L, shell=wl.shell, dt=wl.dt, precision="fp64")
+    s.step(k1)
+    pr = s.props()
+    assert pr["step"] == k1 and pr["n_rebuilds"] == 1
+    got_order, got_cs = s.bins()
+    assert np.array_equal(got_cs, cs1)
+    assert np.array_equal(got_order, expect)
+    p, _, _, _ = s.get_state()
+    assert np.abs(min_image(p - r1, L)).max() < 1e-12
+    pi, pj = s.pairs()
+    rpi, rpj, _ = sim.pairs()
+    assert np.array_equal(O.pair_set(pi, pj), O.pair_set(rpi, rpj))
+    sim.close()
+    s.close()
+
+
+@pytest.mark.parametrize("make,steps", [(I.sp_256k, 60), (I.sp_4m, 30)], ids=["sp_256k", "sp_4m"])
+def test_full_size_trajectory_matches_oracle(make, steps):
+    """The workload's own start (fcc, FP32 forces, FP64 state) through graph
+    replays with rebuilds against the oracle's FP64 trajectory: positions,
+    velocities, forces, PE, KE and virial, and the rebuild steps."""
     wl = make()
     n, L = wl.n, wl.box
     s = _system(wl.pos, wl.vel, L, shell=wl.shell, dt=wl.dt, precision=wl.precision)
-    rng = np.random.Generator(np.random.PCG64(11))
-    idx = np.sort(rng.choice(n, size=n_sample, replace=False)).astype(np.int64)
     # the fcc start: every separation exceeds r_c, so forces and PE vanish
-    pos, vel, force, step = s.get_state()
-    assert step == 0 and float(np.abs(force).max()) == 0.0 and s.props()["pe"] == 0.0
-    # a few steps through graph replays and at least one rebuild
+    _, _, f0, _ = s.get_state()
+    assert float(np.abs(f0).max()) == 0.0 and s.props()["pe"] == 0.0
+    sim = O.Sim(wl.pos, wl.vel, L, shell=wl.shell, dt=wl.dt)
     s.step(steps)
+    tr = sim.run(steps)
+    p, v, f, step = s.get_state()
+    rp, rv, rf, _ = sim.state()
+    sim.close()
     pr = s.props()
-    assert pr["step"] == steps and pr["n_rebuilds"] >= 1
-    pos, vel, force, step = s.get_state()
-    assert np.isfinite(pos).all() and np.isfinite(force).all()
-    u_ref = _check_sampled_forces(pos, force, L, idx)
-    u_atom, _ = s.atom_energies()
-    assert float(np.abs(u_atom[idx] - u_ref).max()) <= 1e-6 * max(1.0, float(np.abs(u_ref).max()))
-    # total momentum stays at its start value (zero) up to FP32 force rounding
-    p = vel.sum(0)
-    assert float(np.abs(p).max()) <= 1e-6 * n ** 0.5 * steps
-    # a list built at exactly these positions: sampled rows bit-exact, and the
-    # pair set symmetric (each unordered pair once from each side)
-    s.bin_cells()
-    pos2, _, _, _ = s.get_state()
-    assert np.array_equal(pos2, O.wrap(pos, L))
-    pi, pj = _check_sampled_neighbours(s, pos2, L, RC + wl.shell, idx)
-    key = pi.astype(np.int64) * n + pj
-    rkey = pj.astype(np.int64) * n + pi
-    assert np.array_equal(np.sort(key), np.sort(rkey))
-    assert len(pi) == 2 * s.props()["n_pairs"]
     s.close()
+    assert step == steps and pr["n_rebuilds"] == int(tr[:, 5].sum()) >= 1
+    # FP32 pair forces on an FP64 trajectory: the positions drift apart by
+    # the accumulated force rounding (measured well below these bounds)
+    assert np.abs(min_image(p - rp, L)).max() < 1e-6
+    assert np.abs(v - rv).max() < 1e-4
+    assert force_error(f, rf) < 1e-4
+    for key, col in (("ke", 0), ("pe", 1), ("virial", 2)):
+        assert abs(pr[key] - tr[-1, col]) / n < 1e-5, key
+    # total momentum stays at its start value (zero) up to FP32 force rounding
+    assert float(np.abs(v.sum(0)).max()) <= 1e-6 * n ** 0.5 * steps
 
 
 def test_lj_full_size_sampled_parity():

@@ -173,13 +173,19 @@ def test_forces_fp64(shell):
 
 
 def test_sc_lattice_closed_form_on_gpu():
-    # PE/N = 0.2352, W/N = 12.9024 for sc at rho = 0.8 (worked in the oracle pins)
+    # PE/N = 0.2352, W/N = 12.9024 for sc at rho = 0.8 (worked in the oracle
+    # pins).  Every pair has the same separation, so FP32 rounding of the pair
+    # terms is systematic here (it does not average out over pairs); held to
+    # the stated bar 1e-6 max(|X/N|, 1) all the same.
     pos, L = I.sc_lattice(20, 0.8)
     vel = np.zeros_like(pos)
     for prec, tol in (("fp32", 1e-6), ("fp64", 1e-12)):
         s = _system(pos, vel, L, shell=0.4, precision=prec)
         pr = s.props()
-        assert abs(pr["pe_per_atom"] - 0.2352) < tol and abs(pr["virial_per_atom"] - 12.9024) < 20 * tol
+        e_pe = abs(pr["pe_per_atom"] - 0.2352)
+        e_w = abs(pr["virial_per_atom"] - 12.9024)
+        print(f"sc lattice {prec}: PE/N error {e_pe:.3e}, W/N error {e_w:.3e}", flush=True)
+        assert e_pe < tol * max(0.2352, 1.0) and e_w < tol * 12.9024
         s.close()
 
 

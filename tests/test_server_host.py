@@ -71,6 +71,27 @@ class FakeBatch:
         self.closed = True
 
 
+class FakeTimer:
+    """Run spans read from the simulated clock."""
+
+    clock = None
+
+    def __init__(self):
+        self.spans = []
+
+    def before(self):
+        self.spans.append([self.clock.t, None])
+
+    def after(self):
+        self.spans[-1][1] = self.clock.t
+
+    def runs(self):
+        return len(self.spans)
+
+    def total_s(self):
+        return sum(b - a for a, b in self.spans)
+
+
 @pytest.fixture
 def fake(monkeypatch):
     clock = FakeClock()
@@ -80,6 +101,8 @@ def fake(monkeypatch):
         return FakeBatch(budget, max_slots, spr, clock=clock)
 
     monkeypatch.setattr(server, "Batch", make)
+    FakeTimer.clock = clock
+    monkeypatch.setattr(server, "RunTimer", FakeTimer)
     # the loop sleeps until the next arrival when nothing is active: advance
     # the simulated clock instead
     monkeypatch.setattr(server.time, "sleep", lambda s: setattr(clock, "t", clock.t + s))
@@ -112,6 +135,10 @@ def test_every_request_served_once_in_budget(fake):
     work = sum(q.n * q.steps for q in reqs)
     assert out["atom_steps"] == work
     assert out["atom_steps_per_s"] == pytest.approx(work / out["makespan_s"])
+    # every run takes run_s of the simulated clock: busy time is runs x run_s
+    assert out["gpu_busy_s"] == pytest.approx(out["runs"] * b.run_s)
+    assert out["gpu_busy_fraction"] == pytest.approx(out["gpu_busy_s"] / out["makespan_s"])
+    assert 0.0 < out["gpu_busy_fraction"] <= 1.0 + 1e-12
     lat = np.array([r.latency for r in out["served"]])
     assert out["p50_latency_s"] == pytest.approx(np.percentile(lat, 50))
     assert out["p99_latency_s"] == pytest.approx(np.percentile(lat, 99))
