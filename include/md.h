@@ -122,6 +122,9 @@ typedef struct {
     int32_t max_cell;       /* largest cell occupancy seen by a sort so far */
     int32_t rebuild_due;    /* 1 if the next step starts with a rebuild */
     int32_t cells_per_edge; /* G */
+    int64_t n_late_bins;    /* rebuilds whose positions the step before had not
+                               binned (the maximum speed jumped): the library
+                               binned them and resumed; results are unchanged */
 } md_props_t;
 
 /* Means over the steps of a block (md_block_begin .. md_block_end). */
@@ -141,14 +144,23 @@ typedef struct {
  * asks for the library's choice.  Out: the values in use. */
 typedef struct {
     int32_t steps_per_run; /* steps per captured graph replay, 1..64 (0: 64) */
-    int32_t grid;          /* workgroups per step-kernel launch, 1..65535 (0: one
-                              per 256-atom tile up to 2048) */
+    int32_t grid;          /* workgroups per step-kernel launch, 1..65535 (0: a
+                              single system one per 256-atom tile up to the
+                              number resident at once, 4 per CU; a batch 2048) */
     int32_t sort_grid;     /* workgroups per sort launch, 1..65535 (0: a single
                               system at most 512, a batch 2048) */
     int32_t sort_split;    /* workgroups sharing one 256-cell tile of the sort,
                               1..32 (0: about 1024 atoms per workgroup for a
                               single system, 1 for a batch) */
+    int32_t tile_order;    /* MD_ORDER_PASSES: in each pass over the tiles the 8
+                              XCDs take consecutive runs of grid/8 tiles;
+                              MD_ORDER_SLABS (0 asks for it): each XCD walks its
+                              own eighth of the tiles, so a tile's neighbours in
+                              z are staged through the same L2 */
 } md_launch_t;
+
+#define MD_ORDER_PASSES 1
+#define MD_ORDER_SLABS 2
 
 typedef struct {
     void *(*alloc)(size_t bytes, void *ctx); /* device memory, >= 256-byte aligned */

@@ -58,12 +58,12 @@ class md_props_t(C.Structure):
                 ("virial_per_atom", C.c_double), ("vmax", C.c_double), ("disp", C.c_double),
                 ("n_pairs", C.c_int64), ("n_rebuilds", C.c_int64), ("step", C.c_int64),
                 ("max_nebr", C.c_int32), ("max_cell", C.c_int32), ("rebuild_due", C.c_int32),
-                ("cells_per_edge", C.c_int32)]
+                ("cells_per_edge", C.c_int32), ("n_late_bins", C.c_int64)]
 
 
 class md_launch_t(C.Structure):
     _fields_ = [("steps_per_run", C.c_int32), ("grid", C.c_int32), ("sort_grid", C.c_int32),
-                ("sort_split", C.c_int32)]
+                ("sort_split", C.c_int32), ("tile_order", C.c_int32)]
 
 
 class md_block_t(C.Structure):

@@ -68,7 +68,14 @@ enum : int32_t {
   ERR_CELL = 2,       // a cell-layer set overflowed beyond its overflow list (repairable)
   ERR_ESCAPED = 4,    // a coordinate outside [-3L/2, 3L/2) when binned
   ERR_NONFINITE = 8,  // NaN / Inf coordinate
+  ERR_UNBINNED = 16,  // the rule fired at a step whose positions were not binned
+                      // ahead (repairable: the host bins them and resumes)
 };
+
+// Binning ahead (see bins_due): r(k) is binned during step k-1 when the
+// displacement rule, accumulated with BIN_AHEAD times the maximum speed of
+// step k-2, would fire at step k.
+constexpr double BIN_AHEAD = 1.5;
 
 // Modes of the step kernel (and of the sort kernel: MODE_STEP or not).
 enum : int32_t {
@@ -123,6 +130,7 @@ struct CtlDev {
   int64_t base;        // `done` when the current graph replay started
   int64_t force_step;  // step whose binning is a rebuild regardless of the rule
   int64_t err_step;    // first step that could not be evaluated
+  int64_t bins_step;   // step whose positions the host binned after ERR_UNBINNED (-1: none)
   int64_t n_rebuilds;  // rebuilds by the displacement rule
   uint64_t vmax_ring[3];  // max v(k)^2 of ring entry k % 3, gathered by k_props (host view)
   double disp_ring[3];    // accumulated displacement after step k, slot k % 3
@@ -141,7 +149,10 @@ struct CtlDev {
 };
 
 // Engine-wide header (device int32[8]).
-enum { HDR_NTILES = 0, HDR_NCTILES = 1, HDR_SPLIT = 2 };  // SPLIT: workgroups per cell tile in k_sort
+enum { HDR_NTILES = 0, HDR_NCTILES = 1, HDR_SPLIT = 2, HDR_ORDER = 3 };
+// SPLIT: workgroups per cell tile in k_sort; ORDER: tile order of the step
+// kernel's workgroups (ORDER_PASSES or ORDER_SLABS, see TileWalk)
+enum { ORDER_PASSES = 0, ORDER_SLABS = 1 };
 
 // Each replica has two descriptors (see SlotDev); CtlDev::var_ring says
 // which one holds a given state.

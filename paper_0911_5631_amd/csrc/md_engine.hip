@@ -146,6 +146,7 @@ struct Replica {
   void *mixbuf = nullptr;
   int nsp = 0;
   std::vector<int32_t> species;
+  int64_t late_bins = 0;  // ERR_UNBINNED repairs
 };
 
 }  // namespace
@@ -170,8 +171,9 @@ struct Engine {
   int grid = 1, cgrid = 1;
   // launch configuration asked for by md_configure / md_batch_configure (0:
   // the library's choice from the sizes; see apply_launch)
-  int grid_req = 0, cgrid_req = 0, split_req = 0;
+  int grid_req = 0, cgrid_req = 0, split_req = 0, order_req = 0;
   int split = 1;                // workgroups per cell tile of the sort in use
+  int resident = MAX_GRID / 2;  // step-kernel workgroups resident at once (4 per CU)
   std::map<int, hipGraphExec_t> graphs;
   bool sticky_hip = false;
   bool verbose = getenv("MD_VERBOSE") != nullptr;
@@ -288,6 +290,11 @@ md_status engine_init(Engine *e, int max_slots, const md_allocator *a, void *str
     e->alloc = *a;
     e->custom_alloc = true;
   }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      cus > 0)
+    e->resident = 4 * cus;
   hipError_t err = hipStreamCreateWithFlags(&e->work, hipStreamNonBlocking);
   if (err == hipSuccess) err = hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming);
   if (err == hipSuccess) err = hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming);
@@ -466,6 +473,7 @@ md_status upload_tables(Engine *e) {
   }
   if (e->split_req > 0) split = e->split_req;
   hdr[HDR_SPLIT] = split;
+  hdr[HDR_ORDER] = e->order_req == MD_ORDER_PASSES ? ORDER_PASSES : ORDER_SLABS;
   for (int s = 0; s < e->max_slots; ++s) {
     Replica *r = e->rep[s];
     if (!r) {
@@ -494,7 +502,9 @@ md_status upload_tables(Engine *e) {
     e->grid = MAX_GRID;
     e->cgrid = MAX_GRID;
   } else {
-    e->grid = std::max(1, std::min(nt, MAX_GRID));
+    // as many step-kernel workgroups as the chip holds at once (four per
+    // CU), each walking its XCD's slab of tiles
+    e->grid = std::max(1, std::min(nt, e->resident));
     e->cgrid = std::max(1, std::min(nct * split, SORT_GRID));
   }
   if (e->grid_req > 0) e->grid = e->grid_req;
@@ -523,6 +533,7 @@ md_status status_of(int err) {
   if (err & ERR_NONFINITE) return MD_ERR_NONFINITE;
   if (err & ERR_ESCAPED) return MD_ERR_ATOM_ESCAPED;
   if (err & ERR_CELL) return MD_ERR_CELL_OVERFLOW;
+  if (err & ERR_UNBINNED) return MD_ERR_STATE;  // repaired by settle(); never expected here
   return MD_OK;
 }
 
@@ -533,16 +544,13 @@ md_status first_error(Engine *e, int only = -1) {
 }
 
 // Wrap, bin and sort the held clean state of the replicas (all, or `only`)
-// into cell order, and bin it again under its new indices (the rows then
-// serve an atom whose neighbour list overflows).
+// into cell order.
 md_status host_sort(Engine *e, int only) {
   Tables T = e->tables();
   launch_clear_set(T, e->cgrid, only, e->work);
   launch_insert(T, e->grid, 1, only, e->work);
   launch_sort(T, e->cgrid, 0, MODE_FORCES, only, e->work);
   launch_flip(T, only, e->work);
-  launch_clear_set(T, e->cgrid, only, e->work);
-  launch_insert(T, e->grid, 0, only, e->work);
   return e->check("sort launches");
 }
 
@@ -643,6 +651,7 @@ void reset_ctl(CtlDev &c, int64_t step, int variant, int64_t n_rebuilds, int max
   c.done = c.target = c.base = step;
   c.force_step = step;
   c.err_step = INT64_MAX;
+  c.bins_step = -1;
   c.n_rebuilds = n_rebuilds;
   c.clean = 1;
   for (int q = 0; q < 3; ++q) c.var_ring[q] = variant;
@@ -687,6 +696,26 @@ md_status repair_cells(Engine *e, int s) {
   c.err_step = INT64_MAX;
   md_status st = upload_tables(e);
   if (st == MD_OK) st = write_ctl(e, s);
+  if (st != MD_OK) return st;
+  launch_insert(e->tables(), e->grid, 0, s, e->work);
+  return e->check("rebin");
+}
+
+// After ERR_UNBINNED in slot s: the displacement rule fired at step
+// done + 1 although the step before did not bin r(done + 1) (the maximum
+// speed grew faster than the binning-ahead guess allows).  The replica holds
+// r(done + 1) unchanged: bin it now and let the sort of that step use the
+// rows (bins_step), then the interrupted steps resume.
+md_status repair_unbinned(Engine *e, int s) {
+  Replica *r = e->rep[s];
+  CtlDev &c = e->h_ctl[s];
+  hipError_t err = clear_sets(e, r);
+  if (err != hipSuccess) return e->fail("rebin", err);
+  c.err &= ~ERR_UNBINNED;
+  c.err_step = INT64_MAX;
+  c.bins_step = c.done + 1;
+  r->late_bins += 1;
+  md_status st = write_ctl(e, s);
   if (st != MD_OK) return st;
   launch_insert(e->tables(), e->grid, 0, s, e->work);
   return e->check("rebin");
@@ -795,8 +824,9 @@ md_status settle(Engine *e) {
     bool repaired = false;
     for (int s = 0; s < e->max_slots; ++s) {
       if (!e->rep[s]) continue;
-      if (e->h_ctl[s].err != ERR_CELL) continue;
-      st = repair_cells(e, s);
+      const int err = e->h_ctl[s].err;
+      if (err != ERR_CELL && err != ERR_UNBINNED) continue;
+      st = err == ERR_CELL ? repair_cells(e, s) : repair_unbinned(e, s);
       if (st == MD_ERR_OOM && e->batch) continue;  // over budget: the slot keeps its error
       if (st != MD_OK) return st;
       repaired = true;
@@ -880,6 +910,7 @@ void fill_props(const Replica *r, const CtlDev &c, md_props_t *o) {
   o->max_nebr = c.max_m;
   o->max_cell = c.max_h;
   o->cells_per_edge = r->g.G;
+  o->n_late_bins = r->late_bins;
   // displacement accumulated through the held step and the rule's decision
   // for the next one (the step kernel recomputes the same from the rings)
   if (!r->g.cell_only && c.clean) {
@@ -1057,7 +1088,8 @@ md_status configure(Engine *e, md_launch_t *cfg) {
   if (!cfg) return MD_ERR_INVALID_ARG;
   if (cfg->steps_per_run < 0 || cfg->steps_per_run > GRAPH_CHUNK || cfg->grid < 0 ||
       cfg->grid > 65535 || cfg->sort_grid < 0 || cfg->sort_grid > 65535 ||
-      cfg->sort_split < 0 || cfg->sort_split > 32)
+      cfg->sort_split < 0 || cfg->sort_split > 32 ||
+      cfg->tile_order < 0 || cfg->tile_order > MD_ORDER_SLABS)
     return MD_ERR_INVALID_ARG;
   if (e->sticky_hip) return MD_ERR_HIP;
   hipError_t err = hipStreamSynchronize(e->work);
@@ -1070,6 +1102,7 @@ md_status configure(Engine *e, md_launch_t *cfg) {
   e->grid_req = cfg->grid;
   e->cgrid_req = cfg->sort_grid;
   e->split_req = cfg->sort_split;
+  e->order_req = cfg->tile_order;
   md_status st = upload_tables(e);
   if (st == MD_OK && !e->batch) st = prepare_graphs(e);
   if (st != MD_OK) return st;
@@ -1077,6 +1110,7 @@ md_status configure(Engine *e, md_launch_t *cfg) {
   cfg->grid = e->grid;
   cfg->sort_grid = e->cgrid;
   cfg->sort_split = e->split;
+  cfg->tile_order = e->order_req == MD_ORDER_PASSES ? MD_ORDER_PASSES : MD_ORDER_SLABS;
   return MD_OK;
 }
 
@@ -1431,8 +1465,23 @@ md_status md_get_cells(md_system *s, int32_t *cell_of_atom) {
   Visit v(e);
   if ((st = v.enter()) != MD_OK) return st;
   if ((st = sync_system(e)) != MD_OK) return st;
-  if ((st = fetch(e, 0, nullptr, nullptr, nullptr, nullptr, nullptr, cell_of_atom)) != MD_OK)
-    return st;
+  // the cells of the held positions, computed on the device into the cell
+  // array of the variant not in use (the next sort overwrites it anyway)
+  Replica *r = e->rep[0];
+  const int h = held_variant(e->h_ctl[0]);
+  int32_t *scratch = r->dev[h ^ 1].cell;
+  launch_cells(e->tables(), e->grid, 0, scratch, e->work);
+  if ((st = e->check("cells")) != MD_OK) return st;
+  const int64_t n = r->g.n;
+  std::vector<int32_t> cell(n), id(n);
+  hipError_t err = hipMemcpyAsync(cell.data(), scratch, (size_t)n * 4, hipMemcpyDeviceToHost,
+                                  e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(id.data(), r->dev[h].id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("get cells", err);
+  for (int64_t p = 0; p < n; ++p)
+    if (id[p] >= 0 && id[p] < n) cell_of_atom[id[p]] = cell[p];
   return v.leave();
 }
 

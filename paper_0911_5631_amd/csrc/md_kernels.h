@@ -34,6 +34,9 @@ void launch_insert(const Tables &T, int grid, int wrap_store, int only, hipStrea
 // or of the held clean state (any other mode; follow with launch_flip).
 void launch_sort(const Tables &T, int cgrid, int step_in_replay, int mode, int only,
                  hipStream_t s);
+// Cell index of every atom of replica `only` at its held position (storage
+// order) into out[n].
+void launch_cells(const Tables &T, int grid, int only, int32_t *out, hipStream_t s);
 // After a sort of the held states: make the sorted variant current.
 void launch_flip(const Tables &T, int only, hipStream_t s);
 // Clear the held state's cell-layer set.

@@ -70,6 +70,33 @@ __device__ __forceinline__ int xcd_block(int b, int g) {
   return b;
 }
 
+// The tiles workgroup b of g takes in a launch over n tiles (t = first;
+// t < end; t += step).  ORDER_PASSES: in pass p the 8 XCDs take consecutive
+// runs of g/8 tiles, XCD x the x-th run of the pass.  ORDER_SLABS: XCD x
+// takes the x-th eighth of all tiles and its workgroups walk it together,
+// g/8 tiles at a time, so the neighbour rows of a tile in z (the halo of its
+// window) are staged by the same XCD shortly before or after it, while its
+// L2 still holds them.  Both visit every tile exactly once.
+struct TileWalk {
+  int t, step, end;
+  __device__ __forceinline__ TileWalk(int b, int g, int n, int order) {
+    if ((g & 7) != 0) {
+      t = b;
+      step = g;
+      end = n;
+    } else if (order == ORDER_SLABS) {
+      const int per = (n + 7) >> 3;
+      t = (b & 7) * per + (b >> 3);
+      step = g >> 3;
+      end = min(n, ((b & 7) + 1) * per);
+    } else {
+      t = (b & 7) * (g >> 3) + (b >> 3);
+      step = g;
+      end = n;
+    }
+  }
+};
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -163,22 +190,31 @@ __device__ __forceinline__ void latch_error(CtlDev &C, int bits, int64_t step) {
   atomicMin((unsigned long long *)&C.err_step, (unsigned long long)step);
 }
 
-// Cell and layer assignment of one atom (Secs. 3.2, 3.4): the atom's cell
-// from its wrapped coordinates, a layer slot from the cell's occupancy
-// counter (atomic), the row entry, or the set's overflow list beyond hcap.
-__device__ __forceinline__ void bin_atom(SlotC &S, CtlDev &C, int set, int i, double x, double y,
-                         double z, int64_t step) {
-  // Called by a prefix of the lanes of a wave (the active atoms of a tile).
+// A new position of step `step`: latch an error for a non-finite coordinate
+// or one outside [-3L/2, 3L/2) (the wrap at the next rebuild could not bring
+// it back); returns false for a non-finite one.
+__device__ __forceinline__ bool check_atom(SlotC &S, CtlDev &C, double x, double y, double z,
+                                           int64_t step) {
   int bad = 0;
   if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
     bad = ERR_NONFINITE;
-    x = y = z = 0.0;
   } else if (fabs(x) >= 3.0 * S.halfL || fabs(y) >= 3.0 * S.halfL || fabs(z) >= 3.0 * S.halfL) {
     bad = ERR_ESCAPED;
   }
   if (bad) latch_error(C, bad, step);
+  return bad != ERR_NONFINITE;
+}
+
+// Cell and layer assignment of one atom (Secs. 3.2, 3.4): the atom's cell
+// from its wrapped coordinates, a layer slot from the cell's occupancy
+// counter (atomic), the row entry, or the set's overflow list beyond hcap.
+// The sort of a rebuild step reads the rows; the cell each atom lands in
+// there is written by the sort itself.
+__device__ __forceinline__ void bin_atom(SlotC &S, CtlDev &C, int set, int i, double x, double y,
+                         double z, int64_t step) {
+  // Called by a prefix of the lanes of a wave (the active atoms of a tile).
+  if (!check_atom(S, C, x, y, z, step)) x = y = z = 0.0;
   const int c = cell_of(S, wrap1(x, S.L, S.halfL), wrap1(y, S.L, S.halfL), wrap1(z, S.L, S.halfL));
-  gp(S.cell)[i] = c;
   // Consecutive lanes with the same cell take their layer slots with one
   // atomic: atoms are stored in cell order, so most of a cell's atoms are
   // neighbours in a wave.
@@ -288,6 +324,27 @@ __device__ __forceinline__ double ring_max(SlotC &S, int64_t e) {
   return wave_max(v);
 }
 
+// Whether r(k) is binned during step k-1, so that a sort at step k finds its
+// rows (binning every step would cost a step's worth of atomics and row
+// writes where a rebuild comes about one step in ten).  Always with the cell
+// method and at a forced rebuild; otherwise when the displacement rule of
+// rebuild_at, accumulated with BIN_AHEAD times the maximum speed of step
+// k-2 (that of step k-1 is not known while step k-1 runs), would fire at
+// step k.  The sort of step k evaluates the same expression from the same
+// committed words, so it knows whether the rows exist; when the rule fires
+// without them (the maximum speed grew by more than BIN_AHEAD in one step)
+// it latches ERR_UNBINNED and the host bins r(k) and resumes, so the
+// trajectory does not depend on the guess.  Called by whole waves.
+template <class Ctl>
+__device__ __forceinline__ bool bins_due(SlotC &S, const Ctl &C, int64_t k) {
+  const double D2 = C.disp_ring[mod3(k - 2)];
+  const double V2 = ring_max(S, mod3(k - 2));
+  if (S.cell_only || k == C.force_step) return true;
+  const bool rb1 = (k - 1 == C.force_step) || D2 > S.half_shell;
+  const double D1 = (rb1 ? 0.0 : D2) + BIN_AHEAD * sqrt(V2) * S.dt;
+  return D1 > S.half_shell;
+}
+
 // Rebuild decision for step k (Sec. 3.1): rebuilt when the accumulated sum
 // of vmax*dt exceeds delta/2.  disp after step k-1 is recomputed from the
 // committed disp after step k-2 and vmax of step k-1; *disp1 receives it.
@@ -314,6 +371,7 @@ __global__ __launch_bounds__(TILE) void k_kick(Tables T) {
     // errors latched by this launch (err_step = done + 1) do not stop it
     if ((C.err != 0 && C.err_step <= C.done) || !C.clean || C.done >= C.target) continue;
     const int64_t k = C.done;
+    const bool bin = bins_due(slot(T, 2 * r), C, k + 1);
     const int i = (t - S.tile_off) * TILE + threadIdx.x;
     if (i >= S.n) continue;
     const int pb = (int)(k & 1), vb = (int)((k + 1) & 1);
@@ -328,7 +386,10 @@ __global__ __launch_bounds__(TILE) void k_kick(Tables T) {
       xn[a] = gp(S.P[pb][a])[i] + S.dt * v;
       gp(S.P[pb ^ 1][a])[i] = xn[a];
     }
-    bin_atom(S, C, (int)mod3(k + 1), i, xn[0], xn[1], xn[2], k + 1);
+    if (bin)
+      bin_atom(S, C, (int)mod3(k + 1), i, xn[0], xn[1], xn[2], k + 1);
+    else
+      check_atom(S, C, xn[0], xn[1], xn[2], k + 1);
   }
 }
 
@@ -372,7 +433,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
   // once for a run of consecutive cell tiles of one replica
   int rc = -1, var = 0;
   int64_t k = 0;
-  bool skip = true, rebuild = false;
+  bool skip = true, rebuild = false, unbinned = false;
   double d1 = 0.0;
   for (int u = xcd_block(blockIdx.x, gridDim.x); u < nunits; u += gridDim.x) {
     const int t = u / nsp, sp = u - t * nsp;
@@ -391,12 +452,14 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
         rebuild = true;
         d1 = 0.0;
         if (!S0.cell_only) rebuild = rebuild_at(S0, C, k, &d1);
+        unbinned = rebuild && !bins_due(S0, C, k) && k != C.bins_step;
       } else {
         if (!C.clean) continue;
         k = C.done;
         if (C.err != 0 && C.err_step <= k) continue;
         var = C.var_ring[mod3(k)];
         rebuild = true;
+        unbinned = false;
       }
       skip = false;
     }
@@ -412,14 +475,19 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
       if (t == S0.ctile_off && sp == 0 && threadIdx.x == 0) {
         // the one writer of these ring slots for step k (with one replica
         // that is unit 0, the first unit of its workgroup, so no workgroup
-        // stops before it)
-        C.rb_ring[mod3(k)] = rebuild ? 1 : 0;
-        if (!S0.cell_only) {
-          C.disp_ring[mod3(k - 1)] = d1;
-          if (rebuild && k != C.force_step) C.n_rebuilds += 1;
+        // stops before it); a step whose rows are missing is stopped here
+        // and done again once the host has binned it
+        if (unbinned) {
+          latch_error(C, ERR_UNBINNED, k);
+        } else {
+          C.rb_ring[mod3(k)] = rebuild ? 1 : 0;
+          if (!S0.cell_only) {
+            C.disp_ring[mod3(k - 1)] = d1;
+            if (rebuild && k != C.force_step) C.n_rebuilds += 1;
+          }
         }
       }
-      if (!rebuild) {
+      if (!rebuild || unbinned) {
         if (solo) break;
         continue;
       }
@@ -973,7 +1041,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
                                                const double *sz, double xi, double yi,
                                                double zi, bool build, bool force, bool energy,
                                                Acc<R> &a, const int8_t *ssp, gcint SP, int spi,
-                                               const PairTab *tab) {
+                                               const PairTab *tab, bool global_only = false) {
   const int G = S.G;
   const double L = S.L, rn2 = S.rn2, rc2 = S.rc2;
   const R ushift = (R)S.ushift;
@@ -982,8 +1050,10 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   const size_t np = (size_t)S.npad;
   const auto CS = cview((const int32_t *)S.cs);  // written by the sort, read-only here
   const int cx = ci % G, cy = (ci / G) % G, cz = ci / (G * G);
-  const int sr = ci / G - w.rf;  // source row of the atom within the tile
-  const bool whole = w.whole, rows = !whole && w.wt[0] >= 0;
+  // global_only: candidates from global memory (the window's row table is
+  // not at hand)
+  const bool whole = !global_only && w.whole, rows = !global_only && !whole && w.wt[0] >= 0;
+  const int sr = rows ? ci / G - w.rf : 0;  // source row of the atom within the tile
   int m = 0;
   // candidates j of [lo, hi); FROM_LDS: every lane of the wave reads the
   // window (the usual case: one code path, the reads of four candidates in
@@ -1089,40 +1159,6 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   return m;
 }
 
-// 27-cell traversal over the cell-layer rows of set `set` (positions of the
-// current step, unsorted since the last rebuild).  Used for an atom whose
-// neighbour list overflowed its capacity at the last build: forces only.
-template <typename R, bool MIX>
-__device__ void traverse_rows(SlotC &S, int set, int i, int ci, gcdouble X, gcdouble Y,
-                              gcdouble Z, double xi, double yi, double zi, Acc<R> &a, gcint SP,
-                              int spi, const PairTab *tab) {
-  const int G = S.G;
-  const double L = S.L, halfL = S.halfL, rc2 = S.rc2;
-  const R ushift = (R)S.ushift;
-  const int cx = ci % G, cy = (ci / G) % G, cz = ci / (G * G);
-  for (int q = 0; q < 27; ++q) {
-    uint32_t ix, iy, iz;
-    const int nx = wrap_cell(cx + q % 3 - 1, G, &ix);
-    const int ny = wrap_cell(cy + (q / 3) % 3 - 1, G, &iy);
-    const int nz = wrap_cell(cz + q / 9 - 1, G, &iz);
-    const int c = (nz * G + ny) * G + nx;
-    const double bx = img_shift(ix, L), by = img_shift(iy, L), bz = img_shift(iz, L);
-    visit_cell(S, set, c, gp(S.cnt[set])[c], [&](int j, int) {
-      if (j == i) return;
-      const double dx = (xi - wrap1(X[j], L, halfL)) + bx;
-      const double dy = (yi - wrap1(Y[j], L, halfL)) + by;
-      const double dz = (zi - wrap1(Z[j], L, halfL)) + bz;
-      const double s = (dx * dx + dy * dy) + dz * dz;
-      if (MIX) {
-        const int kk = (spi * MAXSP + SP[j]) & (MAXSP * MAXSP - 1);
-        if (s < tab->rc2[kk]) pair_accum_mix<R>(a, dx, dy, dz, s, tab, kk, true);
-      } else if (s < rc2) {
-        pair_accum<R>(a, dx, dy, dz, s, ushift, true);
-      }
-    });
-  }
-}
-
 // Coordinates of neighbour-list entry e: from the LDS window, or from
 // global memory when the entry carries a storage index.
 template <bool MIX>
@@ -1174,17 +1210,16 @@ __device__ __forceinline__ void list_pair(Acc<R> &a, bool ok, uint32_t e, double
 // parameters in LDS).
 template <typename R, bool ACC, bool MIX>
 __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k, int mode, bool cells,
-                          bool build, bool last) {
+                          bool build, bool last, bool bin_next) {
   const int i = lt * TILE + threadIdx.x;
   const bool act = i < S.n;
   const int pb = (int)(k & 1);
   const int vb = mode == MODE_STEP ? pb : pb ^ 1;  // v(k-1/2) during a run, v(k) when clean
-  const int set = (int)mod3(k);
   const gcdouble X = gp((const double *)S.P[pb][0]);
   const gcdouble Y = gp((const double *)S.P[pb][1]);
   const gcdouble Z = gp((const double *)S.P[pb][2]);
   const bool force = mode != MODE_BUILD;
-  const double L = S.L, halfL = S.halfL;
+  const double L = S.L;
 
   // loads that do not wait for the window: own position and velocity, list
   // length and the first NE list entries (or the own cell when sorted)
@@ -1305,9 +1340,12 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
         }
       } else {
         // the list overflowed its capacity at the last build: evaluate this
-        // atom from the cell-layer rows of the current positions (exact)
-        traverse_rows<R, MIX>(S, set, i, gp(S.cell)[i], X, Y, Z, wrap1(xi, L, halfL),
-                              wrap1(yi, L, halfL), wrap1(zi, L, halfL), a, SP, spi, tab);
+        // atom over the 27 cells of its cell at that sort, with the positions
+        // of now (exact: an atom within r_c now was within r_n then, since
+        // neither moved more than delta/2), reading them from global memory
+        traverse_sorted<R, MIX>(S, i, gp(S.cell)[i], X, Y, Z, win, sx, sy, sz, xi, yi, zi,
+                                false, true, mode != MODE_STEP || last || ACC, a, ssp, SP, spi,
+                                tab, true);
       }
     }
   }
@@ -1328,7 +1366,10 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
           xn[q] = xo[q] + S.dt * v[q];
           gp(S.P[pb ^ 1][q])[i] = xn[q];
         }
-        bin_atom(S, C, (int)mod3(k + 1), i, xn[0], xn[1], xn[2], k + 1);
+        if (bin_next)
+          bin_atom(S, C, (int)mod3(k + 1), i, xn[0], xn[1], xn[2], k + 1);
+        else
+          check_atom(S, C, xn[0], xn[1], xn[2], k + 1);
       }
       for (int q = 0; q < 3; ++q) gp(S.V[pb ^ 1][q])[i] = v[q];
     }
@@ -1449,8 +1490,9 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
   // launches only (this launch writes other ring slots and err_step > k).
   int rc = -1, var = 0;
   int64_t k = 0;
-  bool skip = true, last = false, cells = false, build = false;
-  for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
+  bool skip = true, last = false, cells = false, build = false, bin_next = false;
+  const TileWalk tw(blockIdx.x, gridDim.x, nt, cview(T.hdr)[HDR_ORDER]);
+  for (int t = tw.t; t < tw.end; t += tw.step) {
     const int r = cview(T.tile_rep)[t];
     if (r != rc) {
       rc = r;
@@ -1468,6 +1510,8 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
         cells = C.rb_ring[mod3(k)] != 0;
         build = cells && !S0.cell_only;
         if (cells) var ^= 1;
+        // r(k+1) is binned here if a sort at step k+1 may need its rows
+        bin_next = !last && bins_due(S0, C, k + 1);
       } else {
         if (!C.clean) continue;
         k = C.done;
@@ -1484,7 +1528,7 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
     CtlDev &C = T.ctl[r];
     SlotC &S = slot(T, 2 * r + var);
     const int lt = t - S.tile_off;
-    step_tile<R, ACC, MIX>(S, C, lt, k, mode, cells, build, last);
+    step_tile<R, ACC, MIX>(S, C, lt, k, mode, cells, build, last, bin_next);
     if (mode == MODE_STEP && lt == 0 && threadIdx.x == 0)
       C.var_ring[mod3(k)] = var;  // the one writer of this ring slot in this launch
     if (mode == MODE_STEP && lt == 0 && threadIdx.x < VSPREAD)
@@ -1645,6 +1689,24 @@ __global__ __launch_bounds__(TILE) void k_insert(Tables T, int wrap_store, int o
   }
 }
 
+// Cell index of the held position of every atom of replica `only`, storage
+// order, into out (md_get_cells): the cell of bin_atom without binning.
+__global__ __launch_bounds__(TILE) void k_cells(Tables T, int only, int32_t *out) {
+  const int nt = T.hdr[HDR_NTILES];
+  for (int t = xcd_block(blockIdx.x, gridDim.x); t < nt; t += gridDim.x) {
+    const int r = T.tile_rep[t];
+    if (r != only || slot(T, 2 * r).n <= 0) continue;
+    SlotC &S = slot_held(T, r);
+    const CtlDev &C = T.ctl[r];
+    const int i = (t - S.tile_off) * TILE + threadIdx.x;
+    if (i >= S.n) continue;
+    const int pb = (int)(cur_state(C) & 1);
+    double x = S.P[pb][0][i], y = S.P[pb][1][i], z = S.P[pb][2][i];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) x = y = z = 0.0;
+    out[i] = cell_of(S, wrap1(x, S.L, S.halfL), wrap1(y, S.L, S.halfL), wrap1(z, S.L, S.halfL));
+  }
+}
+
 // Clear the cell-layer set of the held state (before re-binning it).
 __global__ __launch_bounds__(TILE) void k_clear_set(Tables T, int only) {
   const int nct = T.hdr[HDR_NCTILES];
@@ -1711,6 +1773,9 @@ void launch_adjust(const Tables &T, int grid, int only, double temperature, hipS
 }
 void launch_insert(const Tables &T, int grid, int wrap_store, int only, hipStream_t s) {
   hipLaunchKernelGGL(k_insert, dim3(grid), dim3(TILE), 0, s, T, wrap_store, only);
+}
+void launch_cells(const Tables &T, int grid, int only, int32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cells, dim3(grid), dim3(TILE), 0, s, T, only, out);
 }
 void launch_flip(const Tables &T, int only, hipStream_t s) {
   hipLaunchKernelGGL(k_flip, dim3((T.nslots + TILE - 1) / TILE), dim3(TILE), 0, s, T, only);

@@ -247,10 +247,11 @@ class System:
         return k.value, ms.value
 
     def configure(self, steps_per_run: int = 0, grid: int = 0, sort_grid: int = 0,
-                  sort_split: int = 0) -> Dict[str, int]:
+                  sort_split: int = 0, tile_order: int = 0) -> Dict[str, int]:
         """Launch configuration of later steps (changes no arithmetic); 0 asks
         for the library's choice.  Returns the configuration in use."""
-        cfg = L.md_launch_t(int(steps_per_run), int(grid), int(sort_grid), int(sort_split))
+        cfg = L.md_launch_t(int(steps_per_run), int(grid), int(sort_grid), int(sort_split),
+                            int(tile_order))
         check(lib().md_configure(self._h, C.byref(cfg)), "md_configure")
         return _launch_dict(cfg)
 
@@ -310,10 +311,11 @@ class Batch:
             raise
 
     def configure(self, steps_per_run: int = 0, grid: int = 0, sort_grid: int = 0,
-                  sort_split: int = 0) -> Dict[str, int]:
+                  sort_split: int = 0, tile_order: int = 0) -> Dict[str, int]:
         """Launch configuration of later runs (changes no arithmetic); 0 asks
         for the library's choice.  Returns the configuration in use."""
-        cfg = L.md_launch_t(int(steps_per_run), int(grid), int(sort_grid), int(sort_split))
+        cfg = L.md_launch_t(int(steps_per_run), int(grid), int(sort_grid), int(sort_split),
+                            int(tile_order))
         check(lib().md_batch_configure(self._h, C.byref(cfg)), "md_batch_configure")
         self.steps_per_run = cfg.steps_per_run
         return _launch_dict(cfg)

@@ -8,7 +8,10 @@ every system's trajectory stays bit-identical whatever is chosen:
   grid           workgroups per step-kernel launch (tiles beyond the grid are
                  taken in further passes of the same workgroups);
   sort_grid      workgroups per sort launch;
-  sort_split     workgroups sharing one 256-cell tile of the sort.
+  sort_split     workgroups sharing one 256-cell tile of the sort;
+  tile_order     how the step kernel's workgroups walk the tiles across the 8
+                 XCDs (passes of consecutive runs, or one slab of tiles per
+                 XCD so that z-neighbour rows share an L2).
 
 A batch is tuned on its own admitted mix with real runs (the steps count
 toward the systems' targets).  A trial is scored by the atom-steps the batch
@@ -26,26 +29,28 @@ import os
 import time
 from typing import Dict, Iterable, List, Mapping, Optional
 
-KNOBS = ("steps_per_run", "grid", "sort_grid", "sort_split")
+KNOBS = ("steps_per_run", "grid", "sort_grid", "sort_split", "tile_order")
 
+# tile_order: 1 passes, 2 XCD slabs (0 asks for the library's choice)
 DEFAULT_CANDIDATES = (
-    {"steps_per_run": 16, "grid": 2048, "sort_grid": 2048, "sort_split": 1},
-    {"steps_per_run": 32, "grid": 2048, "sort_grid": 2048, "sort_split": 1},
-    {"steps_per_run": 64, "grid": 2048, "sort_grid": 2048, "sort_split": 1},
-    {"steps_per_run": 64, "grid": 1024, "sort_grid": 2048, "sort_split": 1},
-    {"steps_per_run": 64, "grid": 4096, "sort_grid": 2048, "sort_split": 1},
-    {"steps_per_run": 64, "grid": 2048, "sort_grid": 1024, "sort_split": 1},
-    {"steps_per_run": 64, "grid": 2048, "sort_grid": 4096, "sort_split": 1},
-    {"steps_per_run": 64, "grid": 2048, "sort_grid": 2048, "sort_split": 2},
+    {"steps_per_run": 16, "grid": 2048, "sort_grid": 2048, "sort_split": 1, "tile_order": 1},
+    {"steps_per_run": 32, "grid": 2048, "sort_grid": 2048, "sort_split": 1, "tile_order": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 2048, "sort_split": 1, "tile_order": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 2048, "sort_split": 1, "tile_order": 2},
+    {"steps_per_run": 64, "grid": 1024, "sort_grid": 2048, "sort_split": 1, "tile_order": 2},
+    {"steps_per_run": 64, "grid": 4096, "sort_grid": 2048, "sort_split": 1, "tile_order": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 1024, "sort_split": 1, "tile_order": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 4096, "sort_split": 1, "tile_order": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 2048, "sort_split": 2, "tile_order": 1},
 )
 
 SINGLE_CANDIDATES = (
-    {"steps_per_run": 64, "grid": 0, "sort_grid": 0, "sort_split": 0},
-    {"steps_per_run": 64, "grid": 1024, "sort_grid": 0, "sort_split": 0},
-    {"steps_per_run": 64, "grid": 4096, "sort_grid": 0, "sort_split": 0},
-    {"steps_per_run": 64, "grid": 0, "sort_grid": 256, "sort_split": 0},
-    {"steps_per_run": 64, "grid": 0, "sort_grid": 1024, "sort_split": 0},
-    {"steps_per_run": 32, "grid": 0, "sort_grid": 0, "sort_split": 0},
+    {"steps_per_run": 64, "grid": 0, "sort_grid": 0, "sort_split": 0, "tile_order": 2},
+    {"steps_per_run": 64, "grid": 0, "sort_grid": 0, "sort_split": 0, "tile_order": 1},
+    {"steps_per_run": 64, "grid": 2048, "sort_grid": 0, "sort_split": 0, "tile_order": 2},
+    {"steps_per_run": 64, "grid": 0, "sort_grid": 256, "sort_split": 0, "tile_order": 2},
+    {"steps_per_run": 64, "grid": 0, "sort_grid": 1024, "sort_split": 0, "tile_order": 2},
+    {"steps_per_run": 32, "grid": 0, "sort_grid": 0, "sort_split": 0, "tile_order": 2},
 )
 
 

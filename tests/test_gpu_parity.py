@@ -484,3 +484,47 @@ def test_errors_are_reported():
     with pytest.raises(MDError) as e:
         _system(pos[:10], vel[:10], 3.0, shell=0.4)
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-6)])
+def test_rebuild_the_step_before_did_not_bin_for(precision, tol):
+    """Positions are binned one step ahead only when the displacement rule
+    could fire at the next step, judged from the previous maximum speed.  A
+    lattice nearly at rest with one pair pushed to r = 0.9 and a shell of
+    0.004: the pair's repulsion takes the maximum speed from 0.01 to ~0.7 in
+    one step, so the rule fires at step 2 without rows; the library bins the
+    held positions and resumes.  The trajectory and the rebuild steps equal
+    the oracle's, in a single system and in a batch."""
+    from paper_0911_5631_amd.md import Batch
+    pos, L = I.sc_lattice(8, 0.5)
+    rng = np.random.Generator(np.random.PCG64(61))
+    vel = rng.uniform(-0.005, 0.005, pos.shape)
+    vel -= vel.mean(0)
+    d = pos[1] - pos[0]
+    d -= L * np.round(d / L)
+    pos[0] = pos[1] - d / np.linalg.norm(d) * 0.9
+    n = len(pos)
+    s = _system(pos, vel, L, shell=0.004, precision=precision)
+    sim = O.Sim(pos, vel, L, shell=0.004)
+    s.step(40)
+    tr = sim.run(40)
+    pr = s.props()
+    p, v, _, step = s.get_state()
+    rp, rv, _, _ = sim.state()
+    sim.close()
+    s.close()
+    assert step == 40 and pr["n_late_bins"] >= 1
+    assert pr["n_rebuilds"] == int(tr[:, 5].sum()) >= 2
+    assert np.abs(min_image(p - rp, L)).max() < tol
+    assert abs(pr["pe"] - tr[-1, 1]) / n < 10 * tol
+    b = Batch(1 << 30, 2, 16)
+    slot = b.admit(pos, vel, L, 40, shell=0.004, precision=precision)
+    for _ in range(10):
+        b.run()
+        if b.poll():
+            break
+    bp, bv, bstep = b.get_state(slot)
+    bpr = b.props(slot)
+    b.close()
+    assert bstep == 40 and bpr["n_late_bins"] == pr["n_late_bins"]
+    assert np.array_equal(bp, p) and np.array_equal(bv, v)

@@ -31,8 +31,8 @@ class SimBatch:
         self.log = []
         self.admit_at = None     # (run index, size, target): admit a system then
 
-    def configure(self, steps_per_run=0, grid=0, sort_grid=0, sort_split=0):
-        self.config = (steps_per_run or 64, grid, sort_grid, sort_split)
+    def configure(self, steps_per_run=0, grid=0, sort_grid=0, sort_split=0, tile_order=0):
+        self.config = (steps_per_run or 64, grid, sort_grid, sort_split, tile_order)
         self.log.append(("configure",) + self.config)
         return dict(zip(tune.KNOBS, self.config))
 
@@ -61,7 +61,7 @@ class SimBatch:
         return work, len(running), left
 
 
-def grid_cost(spr, grid, sort_grid, split):
+def grid_cost(spr, grid, sort_grid, split, order=0):
     # ns per atom-step: grid 1024 and sort grid 4096 are the best
     return 0.12 + {1024: 0.0, 2048: 0.01, 4096: 0.03}[grid] + \
         {1024: 0.02, 2048: 0.01, 4096: 0.0}[sort_grid] + 0.005 * (split - 1)
@@ -73,14 +73,14 @@ def test_best_by_atom_steps_per_second(monkeypatch):
     out = tune.autotune(b, runs=3, clock=clock)
     best = out["best"]
     assert (best["grid"], best["sort_grid"]) in {(1024, 2048), (2048, 4096)}
-    assert b.config[:3] == (best["steps_per_run"], best["grid"], best["sort_grid"])
+    assert b.config == tuple(best[k] for k in tune.KNOBS)
     for tr in out["trials"]:
-        spr, g, sg, sp = (tr[k] for k in tune.KNOBS)
-        per_run = 36864 * spr * grid_cost(spr, g, sg, sp) * 1e-9 + 40e-6
+        spr, g, sg, sp, order = (tr[k] for k in tune.KNOBS)
+        per_run = 36864 * spr * grid_cost(spr, g, sg, sp, order) * 1e-9 + 40e-6
         assert tr["atom_steps_per_s"] == pytest.approx(36864 * spr / per_run, rel=1e-9)
     # each candidate: configure, one untimed run, then the timed runs
     for c in tune.DEFAULT_CANDIDATES:
-        cfg = tuple(c[k] for k in tune.KNOBS)
+        cfg = tuple(tune._cfg(c)[k] for k in tune.KNOBS)
         k = b.log.index(("configure",) + cfg)
         assert b.log[k + 1:k + 5] == [("run",) + cfg] * 4
 
