@@ -85,8 +85,14 @@ typedef enum {
 } md_precision;
 
 /* md_params.flags */
-#define MD_EVEN_CELLS 1u /* round G down to even (the rule behind the paper's
-                            cell counts in Tables 1 and 5); default floor(L / r_n) */
+#define MD_EVEN_CELLS 1u  /* round G down to even (the rule behind the paper's
+                             cell counts in Tables 1 and 5); default floor(L / r_n) */
+#define MD_TRACE_PROPS 2u /* record KE, PE, virial and the maximum speed of (e)
+                             for every step of md_step on the device (a ring of
+                             the last 65536 steps; read once with md_get_trace):
+                             the properties the loop of Sec. 3.1 evaluates at
+                             every step, at the cost of summing the energies at
+                             every step */
 
 typedef struct {
     int64_t n_atoms;   /* 1 <= N < 2^25 */
@@ -105,7 +111,7 @@ typedef struct {
     int32_t cell_cap;  /* initial per-cell layer capacity; 0 = from the density:
                           max(16, 2 x the mean occupancy + 8, rounded up to 8)
                           (grown on need) */
-    uint32_t flags;    /* MD_EVEN_CELLS */
+    uint32_t flags;    /* MD_EVEN_CELLS | MD_TRACE_PROPS */
 } md_params;
 
 typedef struct {
@@ -126,6 +132,15 @@ typedef struct {
                                binned (the maximum speed jumped): the library
                                binned them and resumed; results are unchanged */
 } md_props_t;
+
+/* One step of a property trace (MD_TRACE_PROPS): values of (e) of that step. */
+typedef struct {
+    int64_t step;   /* step number (1 = the first step after creation) */
+    double ke;      /* (1/2) sum v^2 */
+    double pe;      /* sum over pairs of u(r) */
+    double virial;  /* sum over pairs of f(r) r^2 */
+    double vmax;    /* max |v| */
+} md_trace_t;
 
 /* Means over the steps of a block (md_block_begin .. md_block_end). */
 typedef struct {
@@ -316,6 +331,12 @@ md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms);
 md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
                         double *build_ms, double *force_ms, int64_t *n_entries);
 
+/* The property trace of steps first_step .. first_step + count - 1 (created
+ * with MD_TRACE_PROPS; at most the last 65536 steps are held): out[q] for
+ * step first_step + q.  MD_ERR_STATE without the flag, or when a requested
+ * step has not been taken yet or has left the ring.  Sync. */
+md_status md_get_trace(md_system *s, int64_t first_step, int64_t count, md_trace_t *out);
+
 /* Launch configuration of later steps (see md_launch_t); the replay graphs
  * are captured again.  *cfg gets the configuration in use.  Sync. */
 md_status md_configure(md_system *s, md_launch_t *cfg);
@@ -359,6 +380,10 @@ md_status md_batch_poll(md_batch *b, int32_t *done, int32_t cap, int32_t *n_done
  * Sync. */
 md_status md_batch_props(md_batch *b, int32_t slot, md_props_t *out);
 md_status md_batch_get_state(md_batch *b, int32_t slot, double *pos, double *vel, int64_t *step);
+
+/* The property trace of the system in a slot (as md_get_trace).  Sync. */
+md_status md_batch_get_trace(md_batch *b, int32_t slot, int64_t first_step, int64_t count,
+                             md_trace_t *out);
 
 /* Free a slot and its device memory.  Sync. */
 md_status md_batch_release(md_batch *b, int32_t slot);

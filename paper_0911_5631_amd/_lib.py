@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmd_gfx950.so")
 MD_FORCE_FP32 = 0
 MD_FORCE_FP64 = 1
 MD_EVEN_CELLS = 1
+MD_TRACE_PROPS = 2
 
 STATUS = {
     0: "MD_OK", -1: "MD_ERR_INVALID_ARG", -2: "MD_ERR_BOX_TOO_SMALL", -3: "MD_ERR_OOM",
@@ -28,9 +29,10 @@ EXPORTS = (
     "md_build_nebr", "md_forces", "md_step", "md_props", "md_get_state",
     "md_get_atom_energies", "md_set_state", "md_get_cells", "md_get_bins", "md_get_pairs",
     "md_adjust_temp", "md_block_begin", "md_block_end", "md_newton3_ab", "md_set_species",
-    "md_profile", "md_kernel_time", "md_configure", "md_destroy", "md_batch_create", "md_batch_admit",
+    "md_profile", "md_kernel_time", "md_configure", "md_get_trace", "md_destroy", "md_batch_create", "md_batch_admit",
     "md_batch_configure", "md_batch_run", "md_batch_poll", "md_batch_props", "md_batch_get_state",
-    "md_batch_release", "md_batch_usage", "md_batch_progress", "md_batch_destroy",
+    "md_batch_release", "md_batch_usage", "md_batch_progress", "md_batch_get_trace",
+    "md_batch_destroy",
 )
 
 
@@ -64,6 +66,11 @@ class md_props_t(C.Structure):
 class md_launch_t(C.Structure):
     _fields_ = [("steps_per_run", C.c_int32), ("grid", C.c_int32), ("sort_grid", C.c_int32),
                 ("sort_split", C.c_int32), ("tile_order", C.c_int32)]
+
+
+class md_trace_t(C.Structure):
+    _fields_ = [("step", C.c_int64), ("ke", C.c_double), ("pe", C.c_double),
+                ("virial", C.c_double), ("vmax", C.c_double)]
 
 
 class md_block_t(C.Structure):
@@ -148,6 +155,11 @@ def lib():
         L.md_batch_admit.argtypes = [_P, C.POINTER(md_params), _D, _D, C.c_int64, _I32]
         L.md_batch_configure.restype = st
         L.md_batch_configure.argtypes = [_P, C.POINTER(md_launch_t)]
+        L.md_get_trace.restype = st
+        L.md_get_trace.argtypes = [_P, C.c_int64, C.c_int64, C.POINTER(md_trace_t)]
+        L.md_batch_get_trace.restype = st
+        L.md_batch_get_trace.argtypes = [_P, C.c_int32, C.c_int64, C.c_int64,
+                                         C.POINTER(md_trace_t)]
         L.md_configure.restype = st
         L.md_configure.argtypes = [_P, C.POINTER(md_launch_t)]
         L.md_batch_run.restype = st

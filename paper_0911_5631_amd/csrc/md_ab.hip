@@ -12,6 +12,8 @@
 // production step kernel is the tuned form of the full side.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "md_device.h"
 #include "md_kernels.h"
 
@@ -139,7 +141,46 @@ __global__ __launch_bounds__(TILE) void k_ab_forces(const double *__restrict__ x
   }
 }
 
+// Zero `words` 32-bit words (a fill kernel rather than a memset node).
+__global__ __launch_bounds__(TILE) void k_ab_zero(uint32_t *__restrict__ p, size_t words) {
+  for (size_t q = (size_t)blockIdx.x * TILE + threadIdx.x; q < words;
+       q += (size_t)gridDim.x * TILE)
+    p[q] = 0u;
+}
+
+// The forces in the caller's order (out[3 id + a], FP64) and the total list
+// length (added to *entries, which must be zero before the launch).
+__global__ __launch_bounds__(TILE) void k_ab_output(const float *__restrict__ F,
+                                                   const int32_t *__restrict__ id,
+                                                   const int32_t *__restrict__ m, int n, int npad,
+                                                   double *__restrict__ out,
+                                                   unsigned long long *entries) {
+  const int p = blockIdx.x * TILE + threadIdx.x;
+  unsigned long long k = 0;
+  if (p < n) {
+    const int i = id[p];
+    if (i >= 0 && i < n)
+      for (int a = 0; a < 3; ++a) out[3 * (size_t)i + a] = (double)F[(size_t)a * npad + p];
+    k = (unsigned long long)m[p];
+  }
+  for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
+  if ((threadIdx.x & 63) == 0 && k) atomicAdd(entries, k);
+}
+
 }  // namespace
+
+void launch_ab_zero(void *p, size_t bytes, hipStream_t s) {
+  const size_t words = bytes / 4;
+  const size_t blocks = std::min<size_t>((words + TILE - 1) / TILE, 4096);
+  hipLaunchKernelGGL(k_ab_zero, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(TILE), 0, s,
+                     (uint32_t *)p, words);
+}
+
+void launch_ab_output(const float *F, const int32_t *id, const int32_t *m, int n, int npad,
+                      double *out, unsigned long long *entries, hipStream_t s) {
+  hipLaunchKernelGGL(k_ab_output, dim3((n + TILE - 1) / TILE), dim3(TILE), 0, s, F, id, m, n,
+                     npad, out, entries);
+}
 
 void launch_ab_build(bool half, const double *x, const double *y, const double *z,
                      const int32_t *cell, const int32_t *cs, int n, int npad, int G, double L,

@@ -51,6 +51,9 @@ constexpr int SORT_GRID = 512;     // sort workgroups of a single system (fewer,
 constexpr int OVF_CAP = 4096;      // per-set overflow list of cell-layer rows
 constexpr int VSPREAD = 32;        // slots of each max-speed ring entry (one per 128-byte line)
 constexpr int MAXSP = 4;           // species of a mixture
+constexpr int MAX_REPLAY = 64;     // steps of the longest replay graph
+constexpr int TRACE_RING = 65536;  // steps held by a replica's property trace
+constexpr int TRACE_W = 5;         // doubles per trace row: step, KE, PE, virial, max v^2
 
 // Pair parameters of a mixture, for species pair k = a * MAXSP + b: Eq. (1)
 // in units of sigma_ab and epsilon_ab, r^2 < rc2 inside the pair's cutoff,
@@ -109,6 +112,9 @@ struct SlotDev {
   double *acc;                      // per-tile sums over the steps of a block [ntiles][NACC]:
                                     // sum v^2, sum u_i, sum w_i, sum m_i
   unsigned long long *vring;        // max v^2 of step k: [k % 3][VSPREAD] slots, 16 words apart
+  double *tpart;                    // traced replica: per-tile KE, PE, virial, max v^2 of
+                                    // step s of the replay, [MAX_REPLAY][ntiles][4] (else null)
+  double *trace;                    // traced replica: [TRACE_RING][TRACE_W], row k % TRACE_RING
   int32_t *sp, *sp_alt;             // mixture: species of each storage position (else null)
   const PairTab *tab;               // mixture: pair parameters (else null)
   double L, halfL, invW, rn2, rc2, dt, hdt, half_shell, ushift, pad0;

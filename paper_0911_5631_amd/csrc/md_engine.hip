@@ -39,7 +39,7 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Geometry {
   int64_t n;
   int G, ncell, ntiles, nctiles, npad, hcap, mcap, cpt;
-  bool cell_only, fp64;
+  bool cell_only, fp64, trace;
   double L, rc, shell, rn;
 };
 
@@ -52,7 +52,8 @@ md_status geometry(const md_params *p, Geometry *g) {
       !std::isfinite(p->shell))
     return MD_ERR_INVALID_ARG;
   if (p->precision != MD_FORCE_FP32 && p->precision != MD_FORCE_FP64) return MD_ERR_INVALID_ARG;
-  if (p->nebr_cap < 0 || p->cell_cap < 0 || (p->flags & ~MD_EVEN_CELLS)) return MD_ERR_INVALID_ARG;
+  if (p->nebr_cap < 0 || p->cell_cap < 0 || (p->flags & ~(MD_EVEN_CELLS | MD_TRACE_PROPS)))
+    return MD_ERR_INVALID_ARG;
   g->n = p->n_atoms;
   g->L = p->box;
   g->rc = p->r_cut;
@@ -60,6 +61,7 @@ md_status geometry(const md_params *p, Geometry *g) {
   g->rn = p->r_cut + p->shell;
   g->cell_only = p->shell == 0.0;
   g->fp64 = p->precision == MD_FORCE_FP64;
+  g->trace = (p->flags & MD_TRACE_PROPS) != 0;
   const double q = std::floor(g->L / g->rn);
   if (q < 3) return MD_ERR_BOX_TOO_SMALL;
   if (q > 1290) return MD_ERR_INVALID_ARG;  // G^3 must fit int32 cell indices
@@ -90,7 +92,7 @@ md_status geometry(const md_params *p, Geometry *g) {
 
 // Layout of the per-replica state block (everything but H and W), in order.
 struct Layout {
-  size_t pv, ids, fu, cellm, cnt, tcnt, cs, win, ovf, part, acc, vring, total;
+  size_t pv, ids, fu, cellm, cnt, tcnt, cs, win, ovf, part, acc, vring, tpart, trace, total;
 };
 // Bytes of one set's cell counters (cnt) and tile counters (tcnt).
 size_t cnt_set_bytes(const Geometry &g) { return round_up((size_t)g.nctiles * CTILE * 4, 256); }
@@ -124,6 +126,13 @@ Layout layout(const Geometry &g) {
   b += round_up((size_t)g.ntiles * NACC * 8, 256);
   l.vring = b;
   b += round_up((size_t)3 * VSPREAD * 16 * 8, 256);
+  l.tpart = l.trace = 0;
+  if (g.trace) {  // MD_TRACE_PROPS: per-step tile partials and the trace ring
+    l.tpart = b;
+    b += round_up((size_t)MAX_REPLAY * g.ntiles * 4 * 8, 256);
+    l.trace = b;
+    b += round_up((size_t)TRACE_RING * TRACE_W * 8, 256);
+  }
   l.total = b;
   return l;
 }
@@ -155,6 +164,9 @@ struct Engine {
   hipStream_t user = nullptr;
   hipStream_t work = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_t[2] = {nullptr, nullptr};  // timing events of the A/B launches
+  void *h_scalar = nullptr;                 // pinned: scalars read back from the device
+  int device = 0;
   md_allocator alloc{};
   bool custom_alloc = false;
   int max_slots = 0;
@@ -181,6 +193,7 @@ struct Engine {
   int steps_per_run = GRAPH_CHUNK;
   int64_t host_target = 0;      // single system: target of the last md_step
   bool accum = false;           // single system: a block is open (steps sum their properties)
+  bool trace = false;           // some admitted replica records a property trace
   int64_t acc_from = 0;         // single system: step at which the open block began
   bool mix = false;             // single system: several species (the mixture kernels)
   int prec = 0;                 // PREC_* bits of the admitted replicas (step-kernel variants)
@@ -291,6 +304,7 @@ md_status engine_init(Engine *e, int max_slots, const md_allocator *a, void *str
     e->custom_alloc = true;
   }
   int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess) e->device = dev;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
       cus > 0)
@@ -298,6 +312,9 @@ md_status engine_init(Engine *e, int max_slots, const md_allocator *a, void *str
   hipError_t err = hipStreamCreateWithFlags(&e->work, hipStreamNonBlocking);
   if (err == hipSuccess) err = hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming);
   if (err == hipSuccess) err = hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming);
+  if (err == hipSuccess) err = hipEventCreate(&e->ev_t[0]);
+  if (err == hipSuccess) err = hipEventCreate(&e->ev_t[1]);
+  if (err == hipSuccess) err = hipHostMalloc(&e->h_scalar, 256, hipHostMallocDefault);
   if (err != hipSuccess) return e->fail("engine init", err);
   e->d_slots = (SlotDev *)e->dmalloc(sizeof(SlotDev) * 2 * max_slots);
   e->d_ctl = (CtlDev *)e->dmalloc(sizeof(CtlDev) * max_slots);
@@ -340,6 +357,9 @@ void engine_free(Engine *e) {
   if (e->h_ctl) (void)hipHostFree(e->h_ctl);
   if (e->h_slots) (void)hipHostFree(e->h_slots);
   if (e->h_tab) (void)hipHostFree(e->h_tab);
+  for (hipEvent_t x : e->ev_t)
+    if (x) (void)hipEventDestroy(x);
+  if (e->h_scalar) (void)hipHostFree(e->h_scalar);
   if (e->ev_in) (void)hipEventDestroy(e->ev_in);
   if (e->ev_out) (void)hipEventDestroy(e->ev_out);
   if (e->work) (void)hipStreamDestroy(e->work);
@@ -380,6 +400,8 @@ void describe(Replica *r) {
   d.part = (double *)(b + l.part);
   d.acc = (double *)(b + l.acc);
   d.vring = (unsigned long long *)(b + l.vring);
+  d.tpart = g.trace ? (double *)(b + l.tpart) : nullptr;
+  d.trace = g.trace ? (double *)(b + l.trace) : nullptr;
   d.W = (int32_t *)r->wmat;
   d.L = g.L;
   d.halfL = 0.5 * g.L;
@@ -429,9 +451,11 @@ md_status upload_tables(Engine *e) {
   hipError_t err = hipStreamSynchronize(e->work);
   if (err != hipSuccess) return e->fail("upload tables", err);
   int nt = 0, nct = 0;
+  e->trace = false;
   for (int s = 0; s < e->max_slots; ++s) {
     Replica *r = e->rep[s];
     if (!r) continue;
+    e->trace = e->trace || r->g.trace;
     for (int v = 0; v < 2; ++v) {
       r->dev[v].tile_off = nt;
       r->dev[v].ctile_off = nct;
@@ -722,7 +746,8 @@ md_status repair_unbinned(Engine *e, int s) {
 }
 
 hipGraphExec_t step_graph(Engine *e, int k) {
-  const int key = ((k * 4 + e->prec) * 2 + (e->accum ? 1 : 0)) * 2 + (e->mix ? 1 : 0);
+  const int key =
+      (((k * 4 + e->prec) * 2 + (e->accum ? 1 : 0)) * 2 + (e->mix ? 1 : 0)) * 2 + (e->trace ? 1 : 0);
   auto it = e->graphs.find(key);
   if (it != e->graphs.end()) return it->second;
   Tables T = e->tables();
@@ -733,10 +758,13 @@ hipGraphExec_t step_graph(Engine *e, int k) {
     e->fail("begin capture", err);
     return nullptr;
   }
+  // a trace (like a block) needs every step's energies: the summing kernels
   for (int s = 0; s < k; ++s) {
     launch_sort(T, e->cgrid, s, MODE_STEP, -1, e->work);
-    launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum, e->mix);
+    launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum || e->trace,
+                e->mix);
   }
+  if (e->trace) launch_trace(T, k, e->work);
   launch_replay_end(T, k, e->work);
   err = hipStreamEndCapture(e->work, &g);
   if (err == hipSuccess) err = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
@@ -787,10 +815,12 @@ md_status replay(Engine *e, int k) {
     for (int s = 0; s < k; ++s) {
       launch_sort(T, e->cgrid, s, MODE_STEP, -1, e->work);
       hipError_t err = hipEventRecord(e->prof_ev[set][s][0], e->work);
-      launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum, e->mix);
+      launch_step(T, e->grid, s, MODE_STEP, 0, -1, e->prec, e->work, e->accum || e->trace,
+                  e->mix);
       if (err == hipSuccess) err = hipEventRecord(e->prof_ev[set][s][1], e->work);
       if (err != hipSuccess) return e->fail("profile event record", err);
     }
+    if (e->trace) launch_trace(T, k, e->work);
     launch_replay_end(T, k, e->work);
     e->prof_pending[set] = k;
     return e->check("profiled step launches");
@@ -954,48 +984,75 @@ md_status set_force_step(Engine *e, int s) {
   return write_ctl(e, s);
 }
 
-// Device scratch of one md_newton3_ab call, released however the call ends.
-struct AbScratch {
-  Engine *e;
-  int32_t *W = nullptr, *M = nullptr;  // list [mcap][npad]; lengths [npad] + overflow count
-  float *F = nullptr;                  // forces [3][npad]
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  explicit AbScratch(Engine *eng) : e(eng) {}
-  ~AbScratch() {
-    for (hipEvent_t x : ev)
-      if (x) (void)hipEventDestroy(x);
-    (void)hipStreamSynchronize(e->work);
-    e->dfree(W);
-    e->dfree(M);
-    e->dfree(F);
-  }
+// Device buffers of one A/B evaluation: the list [mcap][npad], the lengths
+// [npad] followed by the overflow counter, the forces [3][npad] (FP32), the
+// forces in the caller's order (n x 3, FP64) and the summed list length.
+struct AbBufs {
+  int32_t *W = nullptr, *M = nullptr;
+  float *F = nullptr;
+  double *out = nullptr;
+  unsigned long long *entries = nullptr;
 };
 
+// Byte offsets of the AbBufs of one system within one block of memory.
+struct AbLayout {
+  size_t W, M, F, out, entries, total;
+};
+AbLayout ab_layout(const Geometry &g) {
+  AbLayout l{};
+  size_t b = 0;
+  l.W = b;
+  b += round_up((size_t)g.mcap * g.npad * 4, 256);
+  l.M = b;
+  b += round_up((size_t)g.npad * 4 + 256, 256);
+  l.F = b;
+  b += round_up((size_t)3 * g.npad * 4, 256);
+  l.out = b;
+  b += round_up((size_t)3 * g.n * 8, 256);
+  l.entries = b;
+  b += 256;
+  l.total = b;
+  return l;
+}
+AbBufs ab_bufs(void *base, const AbLayout &l) {
+  char *c = (char *)base;
+  AbBufs x;
+  x.W = (int32_t *)(c + l.W);
+  x.M = (int32_t *)(c + l.M);
+  x.F = (float *)(c + l.F);
+  x.out = (double *)(c + l.out);
+  x.entries = (unsigned long long *)(c + l.entries);
+  return x;
+}
+
 // Mean event-timed duration (ms) of `reps` launches of `launch` (with `before`
-// enqueued ahead of each, untimed).
+// enqueued ahead of each, untimed), on the engine's timing events.
 template <class Before, class Launch>
-hipError_t time_launches(Engine *e, hipEvent_t (&ev)[2], int reps, Before &&before,
-                         Launch &&launch, double *mean_ms) {
+hipError_t time_launches(Engine *e, int reps, Before &&before, Launch &&launch,
+                         double *mean_ms) {
   double total = 0.0;
   hipError_t err = hipSuccess;
   for (int k = 0; k < reps && err == hipSuccess; ++k) {
     float ms = 0.f;
-    err = before();
-    if (err == hipSuccess) err = hipEventRecord(ev[0], e->work);
+    before();
+    err = hipGetLastError();
+    if (err == hipSuccess) err = hipEventRecord(e->ev_t[0], e->work);
     if (err == hipSuccess) {
       launch();
       err = hipGetLastError();
     }
-    if (err == hipSuccess) err = hipEventRecord(ev[1], e->work);
-    if (err == hipSuccess) err = hipEventSynchronize(ev[1]);
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (err == hipSuccess) err = hipEventRecord(e->ev_t[1], e->work);
+    if (err == hipSuccess) err = hipEventSynchronize(e->ev_t[1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e->ev_t[0], e->ev_t[1]);
     total += ms;
   }
   *mean_ms = total / reps;
   return err;
 }
 
-md_status newton3_ab(Engine *e, Replica *r, bool half, int reps, double *force,
+// The Newton's-third-law A/B at the held state, into the buffers x (which
+// the caller provides).  Allocates nothing itself.
+md_status newton3_ab(Engine *e, Replica *r, bool half, int reps, const AbBufs &x, double *force,
                      double *build_ms, double *force_ms, int64_t *n_entries) {
   // a fresh sort of the held state (as md_bin_cells), so the cells hold the
   // current positions
@@ -1007,60 +1064,54 @@ md_status newton3_ab(Engine *e, Replica *r, bool half, int reps, double *force,
   const SlotDev &d = r->dev[held_variant(c)];
   const int pb = (int)(c.done & 1);
   const int n = (int)g.n, np = g.npad, mcap = g.mcap;
-  AbScratch x(e);
-  x.W = (int32_t *)e->dmalloc((size_t)mcap * np * 4);
-  x.M = (int32_t *)e->dmalloc((size_t)np * 4 + 256);
-  x.F = (float *)e->dmalloc((size_t)3 * np * 4);
-  if (!x.W || !x.M || !x.F) return MD_ERR_OOM;
   int32_t *dovf = x.M + np;
-  hipError_t err = hipEventCreate(&x.ev[0]);
-  if (err == hipSuccess) err = hipEventCreate(&x.ev[1]);
-  if (err == hipSuccess) err = hipMemsetAsync(dovf, 0, 4, e->work);
+  launch_ab_zero(dovf, 4, e->work);
   double tb = 0.0, tf = 0.0;
+  hipError_t err = time_launches(
+      e, reps, [] {},
+      [&] {
+        launch_ab_build(half, d.P[pb][0], d.P[pb][1], d.P[pb][2], d.cell, d.cs, n, np, g.G, g.L,
+                        g.rn * g.rn, mcap, x.W, x.M, dovf, e->work);
+      },
+      &tb);
   if (err == hipSuccess)
-    err = time_launches(
-        e, x.ev, reps, [] { return hipSuccess; },
-        [&] {
-          launch_ab_build(half, d.P[pb][0], d.P[pb][1], d.P[pb][2], d.cell, d.cs, n, np, g.G,
-                          g.L, g.rn * g.rn, mcap, x.W, x.M, dovf, e->work);
-        },
-        &tb);
-  int32_t ovf = 0;
-  if (err == hipSuccess) err = hipMemcpyAsync(&ovf, dovf, 4, hipMemcpyDeviceToHost, e->work);
+    err = hipMemcpyAsync(e->h_scalar, dovf, 4, hipMemcpyDeviceToHost, e->work);
   if (err == hipSuccess) err = hipStreamSynchronize(e->work);
   if (err != hipSuccess) return e->fail("newton3 a/b build", err);
-  if (ovf != 0) return MD_ERR_NEBR_OVERFLOW;
+  if (*(volatile int32_t *)e->h_scalar != 0) return MD_ERR_NEBR_OVERFLOW;
   // the half form accumulates into F: zero it before every launch
   err = time_launches(
-      e, x.ev, reps,
-      [&] { return half ? hipMemsetAsync(x.F, 0, (size_t)3 * np * 4, e->work) : hipSuccess; },
+      e, reps, [&] { if (half) launch_ab_zero(x.F, (size_t)3 * np * 4, e->work); },
       [&] {
         launch_ab_forces(half, d.P[pb][0], d.P[pb][1], d.P[pb][2], x.W, x.M, n, np, g.L,
                          g.rc * g.rc, x.F, e->work);
       },
       &tf);
-  std::vector<float> hf((size_t)3 * np);
-  std::vector<int32_t> hid(n), hm(n);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(hf.data(), x.F, (size_t)3 * np * 4, hipMemcpyDeviceToHost, e->work);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(hid.data(), d.id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(hm.data(), x.M, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
-  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
   if (err != hipSuccess) return e->fail("newton3 a/b forces", err);
-  int64_t tot = 0;
-  for (int p = 0; p < n; ++p) {
-    tot += hm[p];
-    const int i = hid[p];
-    if (force && i >= 0 && i < n)
-      for (int a = 0; a < 3; ++a) force[3 * (size_t)i + a] = hf[(size_t)a * np + p];
-  }
-  if (n_entries) *n_entries = tot;
+  launch_ab_zero(x.entries, 8, e->work);
+  launch_ab_output(x.F, d.id, x.M, n, np, x.out, x.entries, e->work);
+  if ((err = hipGetLastError()) == hipSuccess && force)
+    err = hipMemcpyAsync(force, x.out, (size_t)3 * n * 8, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(e->h_scalar, x.entries, 8, hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("newton3 a/b output", err);
+  if (n_entries) *n_entries = (int64_t) * (volatile unsigned long long *)e->h_scalar;
   if (build_ms) *build_ms = tb;
   if (force_ms) *force_ms = tf;
   return MD_OK;
 }
+
+// One md_newton3_ab call's allocation, released however the call ends.
+struct AbAlloc {
+  Engine *e;
+  void *p = nullptr;
+  explicit AbAlloc(Engine *eng) : e(eng) {}
+  ~AbAlloc() {
+    (void)hipStreamSynchronize(e->work);
+    e->dfree(p);
+  }
+};
 
 // Upload the species (original order) into the storage order of descriptor
 // variant v, whose id array maps storage positions to original indices.
@@ -1078,6 +1129,36 @@ md_status upload_species(Engine *e, Replica *r, int v) {
   err = hipMemcpyAsync(r->dev[v].sp, sp.data(), (size_t)n * 4, hipMemcpyHostToDevice, e->work);
   if (err == hipSuccess) err = hipStreamSynchronize(e->work);
   return err == hipSuccess ? MD_OK : e->fail("upload species", err);
+}
+
+// Trace rows of steps first .. first + count - 1 of slot s (sync).
+md_status read_trace(Engine *e, int s, int64_t first, int64_t count, md_trace_t *out) {
+  Replica *r = e->rep[s];
+  if (!r->g.trace) return MD_ERR_STATE;
+  if (count < 0 || first < 1 || count > TRACE_RING) return MD_ERR_INVALID_ARG;
+  if (count == 0) return MD_OK;
+  if (!out) return MD_ERR_INVALID_ARG;
+  const double *ring = r->dev[0].trace;
+  std::vector<double> rows((size_t)count * TRACE_W);
+  // at most two contiguous runs of the ring
+  const int64_t a = first % TRACE_RING, n1 = std::min(count, TRACE_RING - a);
+  hipError_t err = hipMemcpyAsync(rows.data(), ring + a * TRACE_W, (size_t)n1 * TRACE_W * 8,
+                                  hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess && n1 < count)
+    err = hipMemcpyAsync(rows.data() + n1 * TRACE_W, ring, (size_t)(count - n1) * TRACE_W * 8,
+                         hipMemcpyDeviceToHost, e->work);
+  if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("read trace", err);
+  for (int64_t q = 0; q < count; ++q) {
+    const double *w = &rows[(size_t)q * TRACE_W];
+    if (w[0] != (double)(first + q)) return MD_ERR_STATE;  // not taken yet, or overwritten
+    out[q].step = first + q;
+    out[q].ke = w[1];
+    out[q].pe = w[2];
+    out[q].virial = w[3];
+    out[q].vmax = std::sqrt(w[4]);
+  }
+  return MD_OK;
 }
 
 // Apply a launch configuration (md_configure / md_batch_configure): the
@@ -1452,7 +1533,12 @@ md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
   Visit v(e);
   if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
-  st = newton3_ab(e, r, half != 0, reps, force, build_ms, force_ms, n_entries);
+  const AbLayout l = ab_layout(r->g);
+  AbAlloc mem(e);
+  mem.p = e->dmalloc(l.total);
+  if (!mem.p) return MD_ERR_OOM;
+  st = newton3_ab(e, r, half != 0, reps, ab_bufs(mem.p, l), force, build_ms, force_ms,
+                  n_entries);
   md_status st2 = v.leave();
   return st != MD_OK ? st : st2;
 }
@@ -1589,6 +1675,17 @@ md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms) {
   *launches = e->prof_launches;
   *total_ms = e->prof_ms;
   return MD_OK;
+}
+
+md_status md_get_trace(md_system *s, int64_t first_step, int64_t count, md_trace_t *out) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  Engine *e = s->e;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
+  if ((st = sync_system(e)) != MD_OK) return st;
+  if ((st = read_trace(e, 0, first_step, count, out)) != MD_OK) return st;
+  return v.leave();
 }
 
 md_status md_configure(md_system *s, md_launch_t *cfg) {
@@ -1747,6 +1844,17 @@ md_status md_batch_get_state(md_batch *b, int32_t slot, double *pos, double *vel
   if ((st = fetch(e, slot, pos, vel, nullptr, nullptr, nullptr, nullptr)) != MD_OK) return st;
   if (step) *step = e->h_ctl[slot].done;
   return status_of(e->h_ctl[slot].err);
+}
+
+md_status md_batch_get_trace(md_batch *b, int32_t slot, int64_t first_step, int64_t count,
+                             md_trace_t *out) {
+  if (!b || !b->e || slot < 0 || slot >= b->e->max_slots || !b->e->rep[slot])
+    return MD_ERR_INVALID_ARG;
+  Engine *e = b->e;
+  if (e->sticky_hip) return MD_ERR_HIP;
+  hipError_t err = hipStreamSynchronize(e->work);
+  if (err != hipSuccess) return e->fail("batch trace", err);
+  return read_trace(e, slot, first_step, count, out);
 }
 
 md_status md_batch_release(md_batch *b, int32_t slot) {

@@ -18,6 +18,9 @@ enum { PREC_FP32 = 1, PREC_FP64 = 2 };
 // replicas have several species.
 void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int force_build,
                  int only, int precisions, hipStream_t s, bool accum = false, bool mix = false);
+// Traced replicas: the properties of the replay's K steps into their trace
+// rings (before launch_replay_end).
+void launch_trace(const Tables &T, int K, hipStream_t s);
 // Advance the step counters after a replay of K steps.
 void launch_replay_end(const Tables &T, int K, hipStream_t s);
 // target = target; base = done (one replica).
@@ -49,6 +52,12 @@ void launch_ab_build(bool half, const double *x, const double *y, const double *
                      const int32_t *cell, const int32_t *cs, int n, int npad, int G, double L,
                      double rn2, int mcap, int32_t *W, int32_t *m, int32_t *overflow,
                      hipStream_t s);
+// Zero device memory with a kernel (bytes a multiple of 4).
+void launch_ab_zero(void *p, size_t bytes, hipStream_t s);
+// The A/B forces in the caller's order (out: n x 3 doubles) and the summed
+// list lengths into *entries (zero before the launch).
+void launch_ab_output(const float *F, const int32_t *id, const int32_t *m, int n, int npad,
+                      double *out, unsigned long long *entries, hipStream_t s);
 void launch_ab_forces(bool half, const double *x, const double *y, const double *z,
                       const int32_t *W, const int32_t *m, int n, int npad, double L, double rc2,
                       float *F, hipStream_t s);

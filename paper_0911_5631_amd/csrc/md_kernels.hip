@@ -1471,6 +1471,16 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
         A[1] = A[1] + (q[2] + q[3]);
         A[2] = A[2] + (q[4] + q[5]);
         A[3] = A[3] + q[6];
+        if (S.tpart) {
+          // a traced replica: this step's tile partials, reduced by k_trace
+          // at the end of the replay
+          const int si = (int)(k - C.base - 1);
+          auto Q = gp(S.tpart) + ((size_t)si * S.ntiles + lt) * 4;
+          Q[0] = q[0];
+          Q[1] = q[2] + q[3];
+          Q[2] = q[4] + q[5];
+          Q[3] = q[1];
+        }
       }
     }
   }
@@ -1533,6 +1543,46 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
       C.var_ring[mod3(k)] = var;  // the one writer of this ring slot in this launch
     if (mode == MODE_STEP && lt == 0 && threadIdx.x < VSPREAD)
       S.vring[(mod3(k + 1) * VSPREAD + threadIdx.x) * 16] = 0ull;
+  }
+}
+
+// End of a graph replay of K steps, before k_replay_end: for every traced
+// replica (workgroup (s, r)) the properties of step base + s + 1, reduced
+// from the tile partials in a fixed order (as k_props), into its trace ring.
+__global__ __launch_bounds__(TILE) void k_trace(Tables T, int K) {
+  const int s = blockIdx.x, r = blockIdx.y;
+  if (s >= K || r >= T.nslots) return;
+  SlotC &S = slot(T, 2 * r);
+  if (S.n <= 0 || S.tpart == nullptr) return;
+  const CtlDev &C = T.ctl[r];
+  const int64_t k = C.base + s + 1;
+  if (k > C.target || (C.err != 0 && C.err_step <= k)) return;
+  __shared__ double sh[TILE][4];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < S.ntiles; t += TILE) {
+    const double *q = S.tpart + ((size_t)s * S.ntiles + t) * 4;
+    v[0] += q[0];
+    v[1] += q[1];
+    v[2] += q[2];
+    v[3] = fmax(v[3], q[3]);
+  }
+  for (int j = 0; j < 4; ++j) sh[threadIdx.x][j] = v[j];
+  __syncthreads();
+  for (int h = TILE / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int j = 0; j < 4; ++j) {
+        const double o = sh[threadIdx.x + h][j];
+        sh[threadIdx.x][j] = j == 3 ? fmax(sh[threadIdx.x][j], o) : sh[threadIdx.x][j] + o;
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double *row = S.trace + (size_t)(k % TRACE_RING) * TRACE_W;
+    row[0] = (double)k;
+    row[1] = 0.5 * sh[0][0];
+    row[2] = 0.5 * sh[0][1];
+    row[3] = 0.5 * sh[0][2];
+    row[4] = sh[0][3];
   }
 }
 
@@ -1758,6 +1808,9 @@ void launch_step(const Tables &T, int grid, int step_in_replay, int mode, int fo
     launch_k_step_r<float>(T, grid, step_in_replay, mode, force_build, only, s, accum, mix);
   if (precisions & PREC_FP64)
     launch_k_step_r<double>(T, grid, step_in_replay, mode, force_build, only, s, accum, mix);
+}
+void launch_trace(const Tables &T, int K, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace, dim3(K, T.nslots), dim3(TILE), 0, s, T, K);
 }
 void launch_replay_end(const Tables &T, int K, hipStream_t s) {
   hipLaunchKernelGGL(k_replay_end, dim3((T.nslots + TILE - 1) / TILE), dim3(TILE), 0, s, T, K);

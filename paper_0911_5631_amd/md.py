@@ -70,10 +70,22 @@ class TorchAllocator:
 
 def make_params(n_atoms: int, box: float, *, r_cut: float = RC_SOFT_SPHERE, shell: float = 0.4,
                 dt: float = 0.005, precision: str = "fp32", nebr_cap: int = 0,
-                cell_cap: int = 0, even_cells: bool = False) -> L.md_params:
+                cell_cap: int = 0, even_cells: bool = False,
+                trace: bool = False) -> L.md_params:
     prec = {"fp32": L.MD_FORCE_FP32, "fp64": L.MD_FORCE_FP64}[precision]
+    flags = (L.MD_EVEN_CELLS if even_cells else 0) | (L.MD_TRACE_PROPS if trace else 0)
     return L.md_params(int(n_atoms), float(box), float(r_cut), float(shell), float(dt), prec,
-                       int(nebr_cap), int(cell_cap), L.MD_EVEN_CELLS if even_cells else 0)
+                       int(nebr_cap), int(cell_cap), flags)
+
+
+def _trace_array(rows) -> np.ndarray:
+    """md_trace_t rows as a structured array (step, ke, pe, virial, vmax)."""
+    out = np.empty(len(rows), dtype=[("step", np.int64), ("ke", np.float64),
+                                     ("pe", np.float64), ("virial", np.float64),
+                                     ("vmax", np.float64)])
+    for k, r in enumerate(rows):
+        out[k] = (r.step, r.ke, r.pe, r.virial, r.vmax)
+    return out
 
 
 def md_cells_per_edge(params: L.md_params) -> int:
@@ -255,6 +267,13 @@ class System:
         check(lib().md_configure(self._h, C.byref(cfg)), "md_configure")
         return _launch_dict(cfg)
 
+    def trace(self, first_step: int, count: int) -> np.ndarray:
+        """Per-step KE, PE, virial and max |v| of steps first_step ..
+        first_step + count - 1 (created with trace=True)."""
+        rows = (L.md_trace_t * max(int(count), 1))()
+        check(lib().md_get_trace(self._h, int(first_step), int(count), rows), "md_get_trace")
+        return _trace_array(rows[:int(count)])
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().md_destroy(self._h)
@@ -343,6 +362,12 @@ class Batch:
         check(lib().md_batch_get_state(self._h, int(slot), _dptr(pos), _dptr(vel),
                                        C.byref(step)), "md_batch_get_state")
         return pos, vel, step.value
+
+    def trace(self, slot: int, first_step: int, count: int) -> np.ndarray:
+        rows = (L.md_trace_t * max(int(count), 1))()
+        check(lib().md_batch_get_trace(self._h, int(slot), int(first_step), int(count), rows),
+              "md_batch_get_trace")
+        return _trace_array(rows[:int(count)])
 
     def release(self, slot: int) -> None:
         check(lib().md_batch_release(self._h, int(slot)), "md_batch_release")
