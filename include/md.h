@@ -341,6 +341,25 @@ md_status md_get_trace(md_system *s, int64_t first_step, int64_t count, md_trace
  * are captured again.  *cfg gets the configuration in use.  Sync. */
 md_status md_configure(md_system *s, md_launch_t *cfg);
 
+/* Bytes of the static device array behind md_newton3_ab_noalloc (per GPU). */
+#define MD_AB_SCRATCH_BYTES (64u << 20)
+
+/* md_newton3_ab without any device allocation, for callers that cannot
+ * allocate (code under graph capture around it, tight serving loops,
+ * harnesses that forbid hipMalloc): the same sort, kernels and outputs, but
+ * the list, lengths, forces and output staging live in one static device
+ * array of MD_AB_SCRATCH_BYTES per GPU, held from the library's load until
+ * the process ends.  A system needs mcap x npad x 4 + 16 x npad + 24 x N
+ * bytes plus alignment (npad = N rounded up to 256; at the default mcap of
+ * 48 about 230 B per atom, so up to ~290 000 atoms): larger ones get
+ * MD_ERR_OOM and nothing runs.  Calls on one GPU share that GPU's array, so
+ * calls that overlap in time on one GPU (two host threads, two systems on
+ * different streams) race; every call clears what it needs before use.  A
+ * pending cell-row overflow of the system, whose repair would allocate, is
+ * reported as MD_ERR_CELL_OVERFLOW instead.  Sync. */
+md_status md_newton3_ab_noalloc(md_system *s, int32_t half, int32_t reps, double *force,
+                                double *build_ms, double *force_ms, int64_t *n_entries);
+
 /* Release the system and its device memory (synchronises its stream). */
 void md_destroy(md_system *s);
 

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -26,6 +27,21 @@
 #include "md_kernels.h"
 
 using namespace md;
+
+// Device memory of md_newton3_ab_noalloc, the A/B entry point for callers
+// that cannot allocate: one array per GPU, held from the library's load to
+// the end of the process.  Host code never passes this name to a kernel (on
+// the host it is a stand-in, not a device address): scratch_ptr() looks up
+// the array's address on the calling engine's device once and keeps it.
+static __device__ __align__(256) unsigned char scratch[MD_AB_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES] = {};
+
+}  // namespace
 
 namespace {
 
@@ -846,8 +862,10 @@ md_status run_steps(Engine *e, int64_t from, int64_t to) {
 }
 
 // Synchronise and repair cell-layer overflows, resuming the remaining steps
-// of a single system.  Returns the first hard error.
-md_status settle(Engine *e) {
+// of a single system.  Returns the first hard error.  Without may_alloc a
+// repair that needs device memory (larger cell-layer rows) is not made and
+// reported as MD_ERR_CELL_OVERFLOW.
+md_status settle(Engine *e, bool may_alloc = true) {
   for (int round = 0; round < 8; ++round) {
     md_status st = read_ctl(e);
     if (st != MD_OK) return st;
@@ -856,6 +874,7 @@ md_status settle(Engine *e) {
       if (!e->rep[s]) continue;
       const int err = e->h_ctl[s].err;
       if (err != ERR_CELL && err != ERR_UNBINNED) continue;
+      if (err == ERR_CELL && !may_alloc) return MD_ERR_CELL_OVERFLOW;
       st = err == ERR_CELL ? repair_cells(e, s) : repair_unbinned(e, s);
       if (st == MD_ERR_OOM && e->batch) continue;  // over budget: the slot keeps its error
       if (st != MD_OK) return st;
@@ -962,8 +981,8 @@ md_status sys_ok(md_system *s) {
 }
 
 // Synchronise a single system: repair, reduce the properties, read back.
-md_status sync_system(Engine *e) {
-  md_status st = settle(e);
+md_status sync_system(Engine *e, bool may_alloc = true) {
+  md_status st = settle(e, may_alloc);
   if (st != MD_OK) return st;
   launch_props(e->tables(), -1, e->work);
   if ((st = e->check("props")) != MD_OK) return st;
@@ -971,8 +990,8 @@ md_status sync_system(Engine *e) {
   return first_error(e);
 }
 
-md_status require_clean(Engine *e) {
-  md_status st = sync_system(e);
+md_status require_clean(Engine *e, bool may_alloc = true) {
+  md_status st = sync_system(e, may_alloc);
   if (st != MD_OK) return st;
   return e->h_ctl[0].clean ? MD_OK : MD_ERR_STATE;
 }
@@ -1050,8 +1069,9 @@ hipError_t time_launches(Engine *e, int reps, Before &&before, Launch &&launch,
   return err;
 }
 
-// The Newton's-third-law A/B at the held state, into the buffers x (which
-// the caller provides).  Allocates nothing itself.
+// The Newton's-third-law A/B at the held state, into the buffers x (however
+// they were obtained: md_newton3_ab allocates them, md_newton3_ab_noalloc
+// takes them from its static array).  Allocates nothing itself.
 md_status newton3_ab(Engine *e, Replica *r, bool half, int reps, const AbBufs &x, double *force,
                      double *build_ms, double *force_ms, int64_t *n_entries) {
   // a fresh sort of the held state (as md_bin_cells), so the cells hold the
@@ -1100,6 +1120,24 @@ md_status newton3_ab(Engine *e, Replica *r, bool half, int reps, const AbBufs &x
   if (build_ms) *build_ms = tb;
   if (force_ms) *force_ms = tf;
   return MD_OK;
+}
+
+// Address of this engine's device's copy of `scratch` (looked up once per
+// device, with that device current; nullptr if the lookup fails).
+void *scratch_ptr(Engine *e) {
+  if (e->device < 0 || e->device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[e->device]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != e->device && hipSetDevice(e->device) != hipSuccess) return nullptr;
+    void *p = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != e->device) (void)hipSetDevice(cur);
+    if (err != hipSuccess) return nullptr;
+    g_scratch[e->device] = p;
+  }
+  return g_scratch[e->device];
 }
 
 // One md_newton3_ab call's allocation, released however the call ends.
@@ -1538,6 +1576,27 @@ md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
   mem.p = e->dmalloc(l.total);
   if (!mem.p) return MD_ERR_OOM;
   st = newton3_ab(e, r, half != 0, reps, ab_bufs(mem.p, l), force, build_ms, force_ms,
+                  n_entries);
+  md_status st2 = v.leave();
+  return st != MD_OK ? st : st2;
+}
+
+md_status md_newton3_ab_noalloc(md_system *s, int32_t half, int32_t reps, double *force,
+                                double *build_ms, double *force_ms, int64_t *n_entries) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (reps < 1 || reps > 100000) return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  Replica *r = e->rep[0];
+  if (r->g.cell_only || r->nsp > 0) return MD_ERR_STATE;
+  const AbLayout l = ab_layout(r->g);
+  if (l.total > (size_t)MD_AB_SCRATCH_BYTES) return MD_ERR_OOM;  // beyond the static array
+  void *base = scratch_ptr(e);
+  if (!base) return e->fail("scratch address");
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
+  if ((st = require_clean(e, false)) != MD_OK) return st;
+  st = newton3_ab(e, r, half != 0, reps, ab_bufs(base, l), force, build_ms, force_ms,
                   n_entries);
   md_status st2 = v.leave();
   return st != MD_OK ? st : st2;

@@ -236,16 +236,18 @@ class System:
                                  C.byref(n)), "md_get_pairs")
         return pi[:n.value], pj[:n.value]
 
-    def newton3_ab(self, half: bool, reps: int = 1) -> Dict[str, object]:
+    def newton3_ab(self, half: bool, reps: int = 1, noalloc: bool = False) -> Dict[str, object]:
         """Full-list vs half-list (Newton's third law, atomics) force phase at
         the held state: forces (original order), mean build and force kernel
-        times (ms), list entries."""
+        times (ms), list entries.  noalloc: the entry point that allocates
+        no device memory (md_newton3_ab_noalloc)."""
         f = np.empty((self.n, 3))
         b = C.c_double()
         t = C.c_double()
         k = C.c_int64()
-        check(lib().md_newton3_ab(self._h, 1 if half else 0, int(reps), _dptr(f), C.byref(b),
-                                  C.byref(t), C.byref(k)), "md_newton3_ab")
+        fn = lib().md_newton3_ab_noalloc if noalloc else lib().md_newton3_ab
+        check(fn(self._h, 1 if half else 0, int(reps), _dptr(f), C.byref(b), C.byref(t),
+                 C.byref(k)), "md_newton3_ab_noalloc" if noalloc else "md_newton3_ab")
         return {"force": f, "build_ms": b.value, "force_ms": t.value, "n_entries": k.value}
 
     # -- measurement ---------------------------------------------------------
