@@ -245,6 +245,44 @@ def lennard_jones(rc: float, n_edge: int, steps: int) -> dict:
             "pe_per_atom": pr["pe_per_atom"], "ke_per_atom": pr["ke_per_atom"]}
 
 
+def no_reorder(marks=(2000, 10000, 100000)) -> dict:
+    """Table 8's experiment: system S (shell 0.6, the Sec. 5.1 equilibration)
+    run with and without reordering; atom-steps/s over the 1000 steps ending
+    at each mark.  Without reordering the atoms keep their start order, which
+    loses its spatial order as they diffuse."""
+    import torch
+    from paper_0911_5631_amd import inputs as I
+    from paper_0911_5631_amd.md import System
+    wl = I.system_s(0.6)
+    n = wl.n
+    out = {"workload": wl.name, "n_atoms": n, "marks": list(marks)}
+    for name, reorder in (("reorder", True), ("no_reorder", False)):
+        s = System(wl.pos, wl.vel, wl.box, shell=wl.shell, dt=wl.dt, even_cells=True,
+                   reorder=reorder)
+        s.equilibrate_run(500, wl.temperature)
+        done = 500
+        rates = []
+        for m in marks:
+            s.step(m - 1000 - done)
+            s.props()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(1000)
+            s.props()
+            rates.append(1000 * n / (time.perf_counter() - t0))
+            done = m
+            print(f"# {name}: steps {m - 1000}-{m}: {rates[-1]:.4g} atom-steps/s",
+                  file=sys.stderr, flush=True)
+        s.close()
+        out[name] = {"atom_steps_per_s": rates,
+                     "us_per_atom_step": [1e6 / r for r in rates]}
+    out["slowdown"] = [a / b for a, b in zip(out["reorder"]["atom_steps_per_s"],
+                                             out["no_reorder"]["atom_steps_per_s"])]
+    # the paper's FX770M figures (Table 8, us per atom-step without reordering)
+    out["paper_no_reorder_us"] = {"1e3": 0.088, "1e5": 0.249}
+    return out
+
+
 def newton3_ab(reps: int) -> dict:
     """The paper's Newton's-third-law trade on this GPU: at an evolved state
     of the 256k soft-sphere bench system and of the LJ r_c = 3.0 system
@@ -437,7 +475,7 @@ def main() -> int:
                     help="time budget of the CPU-oracle sample (0: skip)")
     ap.add_argument("--workload", default="sp_4m",
                     choices=["sp_256k", "sp_4m", "sp_33m", "sp_small", "batch", "served",
-                             "equil", "lj", "newton3", "mixture", "tune"],
+                             "equil", "lj", "newton3", "mixture", "tune", "noreorder"],
                     help="single system (default sp_4m); 'tune' autotunes the single-system "
                          "workloads' launch configuration into the cache; "
                          "'batch' / 'served' run only the full "
@@ -521,6 +559,16 @@ def main() -> int:
                           "n_gpus": 1, "higher_is_better": True, "dtype": "fp32-force/fp64-state",
                           "data": "synthetic (seeded simple cubic start)",
                           "config": {"workload": "lj_rc3.0_110592"}, "lj": runs}), flush=True)
+        return 0
+    if args.workload == "noreorder":
+        r = no_reorder()
+        print(json.dumps({"metric": "atom-steps/s with and without reordering (Table 8)",
+                          "value": r["no_reorder"]["atom_steps_per_s"][-1],
+                          "unit": "atom-steps/s", "n_gpus": 1, "higher_is_better": True,
+                          "dtype": "fp32-force/fp64-state",
+                          "data": "synthetic (seeded simple cubic start)",
+                          "config": {"workload": "no_reorder_" + r["workload"]},
+                          "no_reorder": r}), flush=True)
         return 0
     if args.workload == "mixture":
         r = mixture(4000)

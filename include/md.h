@@ -93,6 +93,16 @@ typedef enum {
                              the properties the loop of Sec. 3.1 evaluates at
                              every step, at the cost of summing the energies at
                              every step */
+#define MD_NO_REORDER 4u  /* never reorder the atoms (the ablation of Table 8):
+                             a rebuild still bins and finds the cell order
+                             (cell_start and a permutation) and wraps the
+                             positions, but every atom keeps its storage
+                             position, so the build reads candidates through
+                             the permutation from global memory and the list
+                             steps gather from wherever the atoms are; the
+                             pair set and forces are those of the reordering
+                             method (the summation order differs).  Not with
+                             md_newton3_ab (MD_ERR_STATE) */
 
 typedef struct {
     int64_t n_atoms;   /* 1 <= N < 2^25 */
@@ -111,7 +121,7 @@ typedef struct {
     int32_t cell_cap;  /* initial per-cell layer capacity; 0 = from the density:
                           max(16, 2 x the mean occupancy + 8, rounded up to 8)
                           (grown on need) */
-    uint32_t flags;    /* MD_EVEN_CELLS | MD_TRACE_PROPS */
+    uint32_t flags;    /* MD_EVEN_CELLS | MD_TRACE_PROPS | MD_NO_REORDER */
 } md_params;
 
 typedef struct {
@@ -294,9 +304,10 @@ md_status md_set_state(md_system *s, const double *pos, const double *vel);
  * original order.  Sync. */
 md_status md_get_cells(md_system *s, int32_t *cell_of_atom);
 
-/* Storage order after the last sort: order[p] = original index of the atom
- * stored at position p; cell_start[c] = first position of cell c,
- * cell_start[G^3] = n (either may be NULL).  Sync. */
+/* Cell order of the last sort: order[p] = original index of the atom at
+ * position p (the storage order; with MD_NO_REORDER the order the sort found,
+ * the atoms themselves staying where they are); cell_start[c] = first
+ * position of cell c, cell_start[G^3] = n (either may be NULL).  Sync. */
 md_status md_get_bins(md_system *s, int32_t *order, int32_t *cell_start);
 
 /* Neighbour-matrix entries as ordered pairs (i, j) of original indices, i

@@ -15,6 +15,7 @@ MD_FORCE_FP32 = 0
 MD_FORCE_FP64 = 1
 MD_EVEN_CELLS = 1
 MD_TRACE_PROPS = 2
+MD_NO_REORDER = 4
 
 STATUS = {
     0: "MD_OK", -1: "MD_ERR_INVALID_ARG", -2: "MD_ERR_BOX_TOO_SMALL", -3: "MD_ERR_OOM",

@@ -115,6 +115,8 @@ struct SlotDev {
   double *tpart;                    // traced replica: per-tile KE, PE, virial, max v^2 of
                                     // step s of the replay, [MAX_REPLAY][ntiles][4] (else null)
   double *trace;                    // traced replica: [TRACE_RING][TRACE_W], row k % TRACE_RING
+  int32_t *perm;                    // MD_NO_REORDER: storage index of the atom at each
+                                    // position of cell order at the last sort (else null)
   int32_t *sp, *sp_alt;             // mixture: species of each storage position (else null)
   const PairTab *tab;               // mixture: pair parameters (else null)
   double L, halfL, invW, rn2, rc2, dt, hdt, half_shell, ushift, pad0;
@@ -125,6 +127,8 @@ struct SlotDev {
   int32_t cpt;       // cells cleared per atom tile: ceil(ncell / ntiles)
   int32_t fp64, cell_only;
   int32_t nsp;       // species of a mixture (0: one species, the r_c / ushift above)
+  int32_t noreo;     // MD_NO_REORDER: a sort finds the cell order (perm, cs) and the
+                     // cells, wraps in place and moves nothing
 };
 
 // Per-replica mutable control block.  Written by the host between launches,

@@ -55,7 +55,7 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Geometry {
   int64_t n;
   int G, ncell, ntiles, nctiles, npad, hcap, mcap, cpt;
-  bool cell_only, fp64, trace;
+  bool cell_only, fp64, trace, noreo;
   double L, rc, shell, rn;
 };
 
@@ -68,7 +68,8 @@ md_status geometry(const md_params *p, Geometry *g) {
       !std::isfinite(p->shell))
     return MD_ERR_INVALID_ARG;
   if (p->precision != MD_FORCE_FP32 && p->precision != MD_FORCE_FP64) return MD_ERR_INVALID_ARG;
-  if (p->nebr_cap < 0 || p->cell_cap < 0 || (p->flags & ~(MD_EVEN_CELLS | MD_TRACE_PROPS)))
+  if (p->nebr_cap < 0 || p->cell_cap < 0 ||
+      (p->flags & ~(MD_EVEN_CELLS | MD_TRACE_PROPS | MD_NO_REORDER)))
     return MD_ERR_INVALID_ARG;
   g->n = p->n_atoms;
   g->L = p->box;
@@ -78,6 +79,7 @@ md_status geometry(const md_params *p, Geometry *g) {
   g->cell_only = p->shell == 0.0;
   g->fp64 = p->precision == MD_FORCE_FP64;
   g->trace = (p->flags & MD_TRACE_PROPS) != 0;
+  g->noreo = (p->flags & MD_NO_REORDER) != 0;
   const double q = std::floor(g->L / g->rn);
   if (q < 3) return MD_ERR_BOX_TOO_SMALL;
   if (q > 1290) return MD_ERR_INVALID_ARG;  // G^3 must fit int32 cell indices
@@ -108,7 +110,7 @@ md_status geometry(const md_params *p, Geometry *g) {
 
 // Layout of the per-replica state block (everything but H and W), in order.
 struct Layout {
-  size_t pv, ids, fu, cellm, cnt, tcnt, cs, win, ovf, part, acc, vring, tpart, trace, total;
+  size_t pv, ids, fu, cellm, cnt, tcnt, cs, win, ovf, part, acc, vring, tpart, trace, perm, total;
 };
 // Bytes of one set's cell counters (cnt) and tile counters (tcnt).
 size_t cnt_set_bytes(const Geometry &g) { return round_up((size_t)g.nctiles * CTILE * 4, 256); }
@@ -148,6 +150,11 @@ Layout layout(const Geometry &g) {
     b += round_up((size_t)MAX_REPLAY * g.ntiles * 4 * 8, 256);
     l.trace = b;
     b += round_up((size_t)TRACE_RING * TRACE_W * 8, 256);
+  }
+  l.perm = 0;
+  if (g.noreo) {  // MD_NO_REORDER: the cell-order permutation of the last sort
+    l.perm = b;
+    b += round_up((size_t)g.npad * 4, 256);
   }
   l.total = b;
   return l;
@@ -418,6 +425,8 @@ void describe(Replica *r) {
   d.vring = (unsigned long long *)(b + l.vring);
   d.tpart = g.trace ? (double *)(b + l.tpart) : nullptr;
   d.trace = g.trace ? (double *)(b + l.trace) : nullptr;
+  d.perm = g.noreo ? (int32_t *)(b + l.perm) : nullptr;
+  d.noreo = g.noreo ? 1 : 0;
   d.W = (int32_t *)r->wmat;
   d.L = g.L;
   d.halfL = 0.5 * g.L;
@@ -1567,7 +1576,7 @@ md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
   if (reps < 1 || reps > 100000) return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
   Replica *r = e->rep[0];
-  if (r->g.cell_only || r->nsp > 0) return MD_ERR_STATE;
+  if (r->g.cell_only || r->nsp > 0 || r->g.noreo) return MD_ERR_STATE;
   Visit v(e);
   if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
@@ -1588,7 +1597,7 @@ md_status md_newton3_ab_noalloc(md_system *s, int32_t half, int32_t reps, double
   if (reps < 1 || reps > 100000) return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
   Replica *r = e->rep[0];
-  if (r->g.cell_only || r->nsp > 0) return MD_ERR_STATE;
+  if (r->g.cell_only || r->nsp > 0 || r->g.noreo) return MD_ERR_STATE;
   const AbLayout l = ab_layout(r->g);
   if (l.total > (size_t)MD_AB_SCRATCH_BYTES) return MD_ERR_OOM;  // beyond the static array
   void *base = scratch_ptr(e);
@@ -1640,7 +1649,20 @@ md_status md_get_bins(md_system *s, int32_t *order, int32_t *cell_start) {
   Replica *r = e->rep[0];
   const SlotDev &d = r->dev[held_variant(e->h_ctl[0])];
   hipError_t err = hipSuccess;
-  if (order) err = hipMemcpyAsync(order, d.id, (size_t)r->g.n * 4, hipMemcpyDeviceToHost, e->work);
+  const int64_t n = r->g.n;
+  if (order && r->g.noreo) {
+    // no reordering: cell order is perm over the (unmoved) storage
+    std::vector<int32_t> perm(n), id(n);
+    err = hipMemcpyAsync(perm.data(), d.perm, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(id.data(), d.id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+    if (err != hipSuccess) return e->fail("get bins", err);
+    for (int64_t p = 0; p < n; ++p)
+      order[p] = perm[p] >= 0 && perm[p] < n ? id[perm[p]] : -1;
+  } else if (order) {
+    err = hipMemcpyAsync(order, d.id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+  }
   if (err == hipSuccess && cell_start)
     err = hipMemcpyAsync(cell_start, d.cs, (size_t)(r->g.ncell + 1) * 4, hipMemcpyDeviceToHost,
                          e->work);

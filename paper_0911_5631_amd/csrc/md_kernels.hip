@@ -542,8 +542,18 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     const int n = S.n;
     const double L = S.L, halfL = S.halfL;
     const bool mixsp = S.nsp > 0;  // a mixture: the species move with the atoms
+    const bool noreo = S.noreo != 0;
     auto move = [&](int a, int cc, int p) {
       if (p >= n || a < 0 || a >= n) return;  // inconsistent counts: never expected
+      if (noreo) {
+        // no reordering: position p of cell order refers to the atom where
+        // it is; it is wrapped in place (read and written by this thread only)
+        gp(S.perm)[p] = a;
+        gp(S.cell)[a] = cc;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gp(S.P[pb][d])[a] = wrap1(gp(S.P[pb][d])[a], L, halfL);
+        return;
+      }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         gp(D.P[pb][d])[p] = wrap1(gp(S.P[pb][d])[a], L, halfL);
@@ -559,7 +569,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     // nsp
     const bool big = c < S.ncell && cnt > 8 && cnt <= min(S.hcap, 8191);
     if (c < S.ncell && cnt > 0 && !big && threadIdx.x % nsp == sp) {
-      if (cnt <= 8 && cnt <= S.hcap) {
+      if (cnt <= 8 && cnt <= S.hcap && !noreo) {
         const int32_t *row = S.H[set] + (size_t)c * S.hcap;
         int v[8];
 #pragma unroll
@@ -597,7 +607,8 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
           }
         }
       } else {
-        // a cell that spilled into the overflow list: repeated minimum searches
+        // a cell that spilled into the overflow list (repeated minimum
+        // searches), and every cell without reordering
         visit_cell(S, set, c, cnt, [&](int a, int q) { move(a, c, base + q); });
       }
     }
@@ -654,7 +665,7 @@ __global__ void k_flip(Tables T, int only) {
   if (r >= T.nslots || (only >= 0 && r != only)) return;
   if (slot(T, 2 * r).n <= 0) return;
   CtlDev &C = T.ctl[r];
-  if (!C.clean) return;
+  if (!C.clean || slot(T, 2 * r).noreo) return;  // no reordering: nothing moved
   const int64_t k = C.done;
   if (C.err != 0 && C.err_step <= k) return;
   C.var_ring[mod3(k)] ^= 1;
@@ -1058,6 +1069,9 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   // candidates j of [lo, hi); FROM_LDS: every lane of the wave reads the
   // window (the usual case: one code path, the reads of four candidates in
   // flight together), else each lane reads where its piece lives
+  // without reordering, position j of cell order is the atom stored at perm[j]
+  const bool noreo = S.noreo != 0;
+  const gcint PERM = gp((const int32_t *)S.perm);
   auto candidates = [&](auto from_lds, int lo, int hi, int delta, uint32_t code, double bx,
                         double by, double bz) {
     // ALL_LDS also means that no lane of the wave applies an image shift
@@ -1065,26 +1079,28 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
     const bool lds = ALL_LDS || delta != NOSLOT;
     for (int j0 = lo; j0 < hi; j0 += 4) {
       double xj[4], yj[4], zj[4];
-      int sj[4];
+      int sj[4], js[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = min(j0 + u, hi - 1);
+        js[u] = j;
         if (ALL_LDS || lds) {
           xj[u] = sx[j + delta];
           yj[u] = sy[j + delta];
           zj[u] = sz[j + delta];
           if (MIX) sj[u] = ssp[j + delta];
         } else {
-          xj[u] = X[j];
-          yj[u] = Y[j];
-          zj[u] = Z[j];
-          if (MIX) sj[u] = SP[j];
+          if (noreo) js[u] = PERM[j];
+          xj[u] = X[js[u]];
+          yj[u] = Y[js[u]];
+          zj[u] = Z[js[u]];
+          if (MIX) sj[u] = SP[js[u]];
         }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + u;
-        if (j >= hi || j == i) continue;
+        if (j >= hi || js[u] == i) continue;
         double dx = xi - xj[u], dy = yi - yj[u], dz = zi - zj[u];
         if (!ALL_LDS) {
           dx = dx + bx;
@@ -1094,7 +1110,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
         const double s = (dx * dx + dy * dy) + dz * dz;
         if (s < rn2) {
           if (build) {
-            const uint32_t idx = lds ? (uint32_t)(j + delta) : ((uint32_t)j | GFLAG);
+            const uint32_t idx = lds ? (uint32_t)(j + delta) : ((uint32_t)js[u] | GFLAG);
             if (m < mcap) Wc[(size_t)m * np] = (int32_t)(idx | code);
             ++m;
           }
@@ -1267,7 +1283,16 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
       ((double *)&stab)[threadIdx.x] = gp((const double *)S.tab)[threadIdx.x];
     if (act) spi = SP[i];
   }
-  if (cells) {
+  if (cells && S.noreo) {
+    // no reordering: the tile's atoms are not a run of cells, so there is no
+    // window; candidates are read from global memory through perm
+    if (threadIdx.x == 0) {
+      win.wt[0] = -1;
+      win.whole = 0;
+      win.rf = 0;
+    }
+    __syncthreads();
+  } else if (cells) {
     make_window(S, lt, win, (int *)sx);
   } else if (list) {
     if (threadIdx.x < WSTRIDE) win.wt[threadIdx.x] = wtv;
@@ -1519,7 +1544,7 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
         // k_sort of this step decided, and if so gathered r(k) into the other variant
         cells = C.rb_ring[mod3(k)] != 0;
         build = cells && !S0.cell_only;
-        if (cells) var ^= 1;
+        if (cells && !S0.noreo) var ^= 1;
         // r(k+1) is binned here if a sort at step k+1 may need its rows
         bin_next = !last && bins_due(S0, C, k + 1);
       } else {
