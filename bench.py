@@ -284,11 +284,13 @@ def no_reorder(marks=(2000, 10000, 100000)) -> dict:
 
 
 def newton3_ab(reps: int) -> dict:
-    """The paper's Newton's-third-law trade on this GPU: at an evolved state
-    of the 256k soft-sphere bench system and of the LJ r_c = 3.0 system
-    (N_e = 48), build a plain storage-index list full or half and time the
-    force loop without reactions (full) and with atomic reactions (half);
-    the production step kernel's list steps are timed beside them."""
+    """The paper's neighbour-list trades on this GPU: at an evolved state of
+    the 256k soft-sphere bench system and of the LJ r_c = 3.0 system (N_e =
+    48), build a plain storage-index list full (atom by atom), half, or full
+    cell by cell (one workgroup per cell, one thread per occupant: Table 3's
+    "old" organisation), and time the builds and the force loop without
+    reactions (full) and with atomic reactions (half); the production step
+    kernel's launches are timed beside them."""
     import torch
     from paper_0911_5631_amd import inputs as I
     from paper_0911_5631_amd.md import System
@@ -311,15 +313,20 @@ def newton3_ab(reps: int) -> dict:
         launches, ms = s.kernel_time()
         s.profile(False)
         pr = s.props()
-        full = s.newton3_ab(False, reps)
-        half = s.newton3_ab(True, reps)
+        full = s.newton3_ab("full", reps)
+        half = s.newton3_ab("half", reps)
+        cells = s.newton3_ab("cells", reps)
         n = len(p)
         out.append({"system": name, "n_atoms": n, "pairs": pr["n_pairs"],
                     "full": {"build_us": full["build_ms"] * 1e3, "force_us": full["force_ms"] * 1e3,
                              "entries": full["n_entries"]},
                     "half": {"build_us": half["build_ms"] * 1e3, "force_us": half["force_ms"] * 1e3,
                              "entries": half["n_entries"]},
+                    "cells": {"build_us": cells["build_ms"] * 1e3,
+                              "force_us": cells["force_ms"] * 1e3,
+                              "entries": cells["n_entries"]},
                     "half_over_full_force": half["force_ms"] / full["force_ms"],
+                    "cells_over_full_build": cells["build_ms"] / full["build_ms"],
                     "step_kernel_mean_us": ms / max(launches, 1) * 1e3})
         s.close()
         torch.cuda.synchronize()

@@ -324,23 +324,42 @@ md_status md_get_pairs(md_system *s, int64_t cap, int32_t *i, int32_t *j, int64_
 md_status md_profile(md_system *s, int32_t enable);
 md_status md_kernel_time(md_system *s, int64_t *launches, double *total_ms);
 
-/* Newton's-third-law A/B of the force phase.  The paper drops Newton's
- * third law on the GPU (Sec. 3.3: full lists, each atom sums its own force)
- * where the CPU keeps each pair once and adds the reaction to the partner
- * (Sec. 3.2).  At the held state, after a fresh sort (as md_bin_cells), this
- * builds a plain neighbour list over the sorted cells -- storage-index
- * entries, r^2 < r_n^2 in FP64 -- full (every j != i) or half (half != 0:
- * j > i, each pair once), then evaluates the pair forces (FP32 on FP64
- * separations, as the step kernel) reps times; the half form adds -f d to
- * the partner with FP32 atomics.  Outputs (each may be NULL): force = the
- * last evaluation's forces (n x 3, original order), build_ms / force_ms =
- * mean event-timed durations of the build and force kernels over reps
- * launches each, n_entries = list entries (2 x pairs full, pairs half).
- * The list capacity is nebr_cap; MD_ERR_NEBR_OVERFLOW if a list exceeds
- * it.  MD_ERR_STATE in cell-list-only mode and for mixtures.  Leaves the
+/* Variants of the neighbour-list A/B (md_newton3_ab, md_ab_pairs). */
+typedef enum {
+    MD_AB_FULL = 0,  /* full list (every j != i), one thread per atom */
+    MD_AB_HALF = 1,  /* half list (j > i, each pair once), reactions by atomics */
+    MD_AB_CELLS = 2  /* full list built cell by cell: one workgroup per cell,
+                        one thread per occupant H_{c,l}, the 27 neighbouring
+                        cells staged in LDS -- the organisation of the earlier
+                        GPU codes the paper compares with at the end of
+                        Sec. 3.4 (Table 3 "old"); the same list as MD_AB_FULL */
+} md_ab_variant;
+
+/* Neighbour-list A/B of the build and force phases.  The paper drops
+ * Newton's third law on the GPU (Sec. 3.3: full lists, each atom sums its
+ * own force) where the CPU keeps each pair once and adds the reaction to
+ * the partner (Sec. 3.2), and builds its list atom by atom rather than cell
+ * by cell (end of Sec. 3.4).  At the held state, after a fresh sort (as
+ * md_bin_cells), this builds a plain neighbour list over the sorted cells --
+ * storage-index entries, r^2 < r_n^2 in FP64 -- in the md_ab_variant given,
+ * then evaluates the pair forces (FP32 on FP64 separations, as the step
+ * kernel) reps times; the half form adds -f d to the partner with FP32
+ * atomics.  Outputs (each may be NULL): force = the last evaluation's forces
+ * (n x 3, original order), build_ms / force_ms = mean event-timed durations
+ * of the build and force kernels over reps launches each, n_entries = list
+ * entries (2 x pairs full, pairs half).  The list capacity is nebr_cap;
+ * MD_ERR_NEBR_OVERFLOW if a list exceeds it.  MD_ERR_STATE in
+ * cell-list-only mode, for mixtures and with MD_NO_REORDER.  Leaves the
  * system as md_bin_cells does.  Sync. */
-md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
+md_status md_newton3_ab(md_system *s, int32_t variant, int32_t reps, double *force,
                         double *build_ms, double *force_ms, int64_t *n_entries);
+
+/* The list of one md_ab_variant built at the held state (as md_newton3_ab)
+ * as ordered pairs (i, j) of original indices: stores at most cap, *n gets
+ * the total (2 x pairs for the full variants, pairs for the half one).
+ * Sync. */
+md_status md_ab_pairs(md_system *s, int32_t variant, int64_t cap, int32_t *i, int32_t *j,
+                      int64_t *n);
 
 /* The property trace of steps first_step .. first_step + count - 1 (created
  * with MD_TRACE_PROPS; at most the last 65536 steps are held): out[q] for
@@ -368,7 +387,7 @@ md_status md_configure(md_system *s, md_launch_t *cfg);
  * different streams) race; every call clears what it needs before use.  A
  * pending cell-row overflow of the system, whose repair would allocate, is
  * reported as MD_ERR_CELL_OVERFLOW instead.  Sync. */
-md_status md_newton3_ab_noalloc(md_system *s, int32_t half, int32_t reps, double *force,
+md_status md_newton3_ab_noalloc(md_system *s, int32_t variant, int32_t reps, double *force,
                                 double *build_ms, double *force_ms, int64_t *n_entries);
 
 /* Release the system and its device memory (synchronises its stream). */

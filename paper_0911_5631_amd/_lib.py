@@ -16,6 +16,7 @@ MD_FORCE_FP64 = 1
 MD_EVEN_CELLS = 1
 MD_TRACE_PROPS = 2
 MD_NO_REORDER = 4
+AB_VARIANTS = {"full": 0, "half": 1, "cells": 2}
 
 STATUS = {
     0: "MD_OK", -1: "MD_ERR_INVALID_ARG", -2: "MD_ERR_BOX_TOO_SMALL", -3: "MD_ERR_OOM",
@@ -30,7 +31,7 @@ EXPORTS = (
     "md_build_nebr", "md_forces", "md_step", "md_props", "md_get_state",
     "md_get_atom_energies", "md_set_state", "md_get_cells", "md_get_bins", "md_get_pairs",
     "md_adjust_temp", "md_block_begin", "md_block_end", "md_newton3_ab",
-    "md_newton3_ab_noalloc", "md_set_species",
+    "md_newton3_ab_noalloc", "md_ab_pairs", "md_set_species",
     "md_profile", "md_kernel_time", "md_configure", "md_get_trace", "md_destroy", "md_batch_create", "md_batch_admit",
     "md_batch_configure", "md_batch_run", "md_batch_poll", "md_batch_props", "md_batch_get_state",
     "md_batch_release", "md_batch_usage", "md_batch_progress", "md_batch_get_trace",
@@ -132,6 +133,8 @@ def lib():
         L.md_set_species.argtypes = [_P, C.c_int32, _I32, _D, _D, _D, _D]
         L.md_newton3_ab.restype = st
         L.md_newton3_ab.argtypes = [_P, C.c_int32, C.c_int32, _D, _D, _D, _I64]
+        L.md_ab_pairs.restype = st
+        L.md_ab_pairs.argtypes = [_P, C.c_int32, C.c_int64, _I32, _I32, _I64]
         L.md_newton3_ab_noalloc.restype = st
         L.md_newton3_ab_noalloc.argtypes = [_P, C.c_int32, C.c_int32, _D, _D, _D, _I64]
         L.md_get_state.restype = st

@@ -89,6 +89,86 @@ __global__ __launch_bounds__(TILE) void k_ab_build(const double *__restrict__ x,
   if (cnt > mcap) atomicAdd(overflow, 1);
 }
 
+// The cell-centric build of the earlier GPU codes (the organisation the
+// paper describes at the end of Sec. 3.4 and times as "old" in Table 3):
+// one workgroup per cell, one thread per occupant (layer l of H_{c,l}) of
+// the cell.  For each of the 27 neighbouring cells in turn the workgroup
+// loads that cell's atoms into LDS and every thread tests its own atom
+// against them.  Only the cell's occupants have work (a few for the soft
+// spheres, up to ~50 for the longest LJ cutoff), so most lanes of the wave
+// idle: the scaling limit the paper points out.  Entries come in the order
+// of k_ab_build<false> (offsets z-major, x fastest; ascending storage index
+// within a cell), so the two lists are identical.
+__global__ __launch_bounds__(64) void k_ab_build_cells(const double *__restrict__ x,
+                                                      const double *__restrict__ y,
+                                                      const double *__restrict__ z,
+                                                      const int32_t *__restrict__ cs, int npad,
+                                                      int G, double L, double rn2, int mcap,
+                                                      int32_t *__restrict__ W,
+                                                      int32_t *__restrict__ m,
+                                                      int32_t *__restrict__ overflow) {
+  __shared__ double sx[64], sy[64], sz[64];
+  const int c = blockIdx.x;
+  const int lo = cs[c], cnt = cs[c + 1] - lo;
+  const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+  for (int l0 = 0; l0 < cnt; l0 += 64) {  // cells of more than 64 occupants in chunks
+    const bool own = l0 + (int)threadIdx.x < cnt;
+    const int i = lo + l0 + threadIdx.x;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    if (own) {
+      xi = x[i];
+      yi = y[i];
+      zi = z[i];
+    }
+    int k = 0;
+    for (int oz = -1; oz <= 1; ++oz) {
+      uint32_t kz;
+      const int nz = ab_wrap(cz + oz, G, &kz);
+      const double bz = ab_shift(kz, L);
+      for (int oy = -1; oy <= 1; ++oy) {
+        uint32_t ky;
+        const int ny = ab_wrap(cy + oy, G, &ky);
+        const double by = ab_shift(ky, L);
+        for (int ox = -1; ox <= 1; ++ox) {
+          uint32_t kx;
+          const int nx = ab_wrap(cx + ox, G, &kx);
+          const double bx = ab_shift(kx, L);
+          const uint32_t code = kx | (ky << 2) | (kz << 4);
+          const int cc = (nz * G + ny) * G + nx;
+          const int lo2 = cs[cc], cnt2 = cs[cc + 1] - lo2;
+          for (int j0 = 0; j0 < cnt2; j0 += 64) {
+            __syncthreads();
+            if (j0 + (int)threadIdx.x < cnt2) {
+              sx[threadIdx.x] = x[lo2 + j0 + threadIdx.x];
+              sy[threadIdx.x] = y[lo2 + j0 + threadIdx.x];
+              sz[threadIdx.x] = z[lo2 + j0 + threadIdx.x];
+            }
+            __syncthreads();
+            const int nj = min(64, cnt2 - j0);
+            if (own) {
+              for (int q = 0; q < nj; ++q) {
+                const int j = lo2 + j0 + q;
+                if (j == i) continue;
+                const double dx = (xi - sx[q]) + bx, dy = (yi - sy[q]) + by,
+                             dz = (zi - sz[q]) + bz;
+                const double s = (dx * dx + dy * dy) + dz * dz;
+                if (s < rn2) {
+                  if (k < mcap) W[(size_t)k * npad + i] = (int32_t)((uint32_t)j | (code << J_BITS));
+                  ++k;
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    if (own) {
+      m[i] = min(k, mcap);
+      if (k > mcap) atomicAdd(overflow, 1);
+    }
+  }
+}
+
 // One thread per atom i: Eq. (1) (with the soft-sphere shift only in the
 // energy, not computed here) in FP32 on FP64 separations, for the entries of
 // i's list.  Full: the sum is i's force, stored once.  Half: the reaction
@@ -193,6 +273,13 @@ void launch_ab_build(bool half, const double *x, const double *y, const double *
   else
     hipLaunchKernelGGL(k_ab_build<false>, grid, dim3(TILE), 0, s, x, y, z, cell, cs, n, npad, G,
                        L, rn2, mcap, W, m, overflow);
+}
+
+void launch_ab_build_cells(const double *x, const double *y, const double *z, const int32_t *cs,
+                           int npad, int G, double L, double rn2, int mcap, int32_t *W,
+                           int32_t *m, int32_t *overflow, hipStream_t s) {
+  hipLaunchKernelGGL(k_ab_build_cells, dim3(G * G * G), dim3(64), 0, s, x, y, z, cs, npad, G, L,
+                     rn2, mcap, W, m, overflow);
 }
 
 void launch_ab_forces(bool half, const double *x, const double *y, const double *z,

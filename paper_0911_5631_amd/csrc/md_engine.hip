@@ -1081,8 +1081,17 @@ hipError_t time_launches(Engine *e, int reps, Before &&before, Launch &&launch,
 // The Newton's-third-law A/B at the held state, into the buffers x (however
 // they were obtained: md_newton3_ab allocates them, md_newton3_ab_noalloc
 // takes them from its static array).  Allocates nothing itself.
-md_status newton3_ab(Engine *e, Replica *r, bool half, int reps, const AbBufs &x, double *force,
-                     double *build_ms, double *force_ms, int64_t *n_entries) {
+// Entries of the A/B list as (i, j) original indices (md_ab_pairs).
+struct AbPairsOut {
+  int64_t cap = 0;
+  int32_t *pi = nullptr, *pj = nullptr;
+  int64_t *n = nullptr;
+};
+
+md_status newton3_ab(Engine *e, Replica *r, int variant, int reps, const AbBufs &x,
+                     double *force, double *build_ms, double *force_ms, int64_t *n_entries,
+                     const AbPairsOut *pairs = nullptr) {
+  const bool half = variant == MD_AB_HALF;
   // a fresh sort of the held state (as md_bin_cells), so the cells hold the
   // current positions
   md_status st = evaluate_clean(e, -1, MODE_FORCES, 1);
@@ -1099,8 +1108,12 @@ md_status newton3_ab(Engine *e, Replica *r, bool half, int reps, const AbBufs &x
   hipError_t err = time_launches(
       e, reps, [] {},
       [&] {
-        launch_ab_build(half, d.P[pb][0], d.P[pb][1], d.P[pb][2], d.cell, d.cs, n, np, g.G, g.L,
-                        g.rn * g.rn, mcap, x.W, x.M, dovf, e->work);
+        if (variant == MD_AB_CELLS)
+          launch_ab_build_cells(d.P[pb][0], d.P[pb][1], d.P[pb][2], d.cs, np, g.G, g.L,
+                                g.rn * g.rn, mcap, x.W, x.M, dovf, e->work);
+        else
+          launch_ab_build(half, d.P[pb][0], d.P[pb][1], d.P[pb][2], d.cell, d.cs, n, np, g.G,
+                          g.L, g.rn * g.rn, mcap, x.W, x.M, dovf, e->work);
       },
       &tb);
   if (err == hipSuccess)
@@ -1108,6 +1121,28 @@ md_status newton3_ab(Engine *e, Replica *r, bool half, int reps, const AbBufs &x
   if (err == hipSuccess) err = hipStreamSynchronize(e->work);
   if (err != hipSuccess) return e->fail("newton3 a/b build", err);
   if (*(volatile int32_t *)e->h_scalar != 0) return MD_ERR_NEBR_OVERFLOW;
+  if (pairs) {
+    // the list as it stands, in original indices
+    std::vector<int32_t> W((size_t)mcap * np), M(n), id(n);
+    err = hipMemcpyAsync(W.data(), x.W, W.size() * 4, hipMemcpyDeviceToHost, e->work);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(M.data(), x.M, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(id.data(), d.id, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->work);
+    if (err != hipSuccess) return e->fail("a/b pairs", err);
+    int64_t k = 0;
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < M[p]; ++q) {
+        const int j = (int)((uint32_t)W[(size_t)q * np + p] & IDX_MASK);
+        if (k < pairs->cap) {
+          pairs->pi[k] = id[p];
+          pairs->pj[k] = j < n ? id[j] : -1;
+        }
+        ++k;
+      }
+    *pairs->n = k;
+  }
   // the half form accumulates into F: zero it before every launch
   err = time_launches(
       e, reps, [&] { if (half) launch_ab_zero(x.F, (size_t)3 * np * 4, e->work); },
@@ -1569,11 +1604,12 @@ md_status md_set_species(md_system *s, int32_t n_species, const int32_t *species
   return v.leave();
 }
 
-md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
+md_status md_newton3_ab(md_system *s, int32_t variant, int32_t reps, double *force,
                         double *build_ms, double *force_ms, int64_t *n_entries) {
   md_status st = sys_ok(s);
   if (st != MD_OK) return st;
-  if (reps < 1 || reps > 100000) return MD_ERR_INVALID_ARG;
+  if (reps < 1 || reps > 100000 || variant < MD_AB_FULL || variant > MD_AB_CELLS)
+    return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
   Replica *r = e->rep[0];
   if (r->g.cell_only || r->nsp > 0 || r->g.noreo) return MD_ERR_STATE;
@@ -1584,17 +1620,44 @@ md_status md_newton3_ab(md_system *s, int32_t half, int32_t reps, double *force,
   AbAlloc mem(e);
   mem.p = e->dmalloc(l.total);
   if (!mem.p) return MD_ERR_OOM;
-  st = newton3_ab(e, r, half != 0, reps, ab_bufs(mem.p, l), force, build_ms, force_ms,
-                  n_entries);
+  st = newton3_ab(e, r, variant, reps, ab_bufs(mem.p, l), force, build_ms, force_ms, n_entries);
   md_status st2 = v.leave();
   return st != MD_OK ? st : st2;
 }
 
-md_status md_newton3_ab_noalloc(md_system *s, int32_t half, int32_t reps, double *force,
+md_status md_ab_pairs(md_system *s, int32_t variant, int64_t cap, int32_t *pi, int32_t *pj,
+                      int64_t *n_out) {
+  md_status st = sys_ok(s);
+  if (st != MD_OK) return st;
+  if (!n_out || cap < 0 || (cap > 0 && (!pi || !pj)) || variant < MD_AB_FULL ||
+      variant > MD_AB_CELLS)
+    return MD_ERR_INVALID_ARG;
+  Engine *e = s->e;
+  Replica *r = e->rep[0];
+  if (r->g.cell_only || r->nsp > 0 || r->g.noreo) return MD_ERR_STATE;
+  Visit v(e);
+  if ((st = v.enter()) != MD_OK) return st;
+  if ((st = require_clean(e)) != MD_OK) return st;
+  const AbLayout l = ab_layout(r->g);
+  AbAlloc mem(e);
+  mem.p = e->dmalloc(l.total);
+  if (!mem.p) return MD_ERR_OOM;
+  AbPairsOut out;
+  out.cap = cap;
+  out.pi = pi;
+  out.pj = pj;
+  out.n = n_out;
+  st = newton3_ab(e, r, variant, 1, ab_bufs(mem.p, l), nullptr, nullptr, nullptr, nullptr, &out);
+  md_status st2 = v.leave();
+  return st != MD_OK ? st : st2;
+}
+
+md_status md_newton3_ab_noalloc(md_system *s, int32_t variant, int32_t reps, double *force,
                                 double *build_ms, double *force_ms, int64_t *n_entries) {
   md_status st = sys_ok(s);
   if (st != MD_OK) return st;
-  if (reps < 1 || reps > 100000) return MD_ERR_INVALID_ARG;
+  if (reps < 1 || reps > 100000 || variant < MD_AB_FULL || variant > MD_AB_CELLS)
+    return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
   Replica *r = e->rep[0];
   if (r->g.cell_only || r->nsp > 0 || r->g.noreo) return MD_ERR_STATE;
@@ -1605,8 +1668,7 @@ md_status md_newton3_ab_noalloc(md_system *s, int32_t half, int32_t reps, double
   Visit v(e);
   if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e, false)) != MD_OK) return st;
-  st = newton3_ab(e, r, half != 0, reps, ab_bufs(base, l), force, build_ms, force_ms,
-                  n_entries);
+  st = newton3_ab(e, r, variant, reps, ab_bufs(base, l), force, build_ms, force_ms, n_entries);
   md_status st2 = v.leave();
   return st != MD_OK ? st : st2;
 }

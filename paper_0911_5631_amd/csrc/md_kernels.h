@@ -52,6 +52,11 @@ void launch_ab_build(bool half, const double *x, const double *y, const double *
                      const int32_t *cell, const int32_t *cs, int n, int npad, int G, double L,
                      double rn2, int mcap, int32_t *W, int32_t *m, int32_t *overflow,
                      hipStream_t s);
+// The cell-centric full list (one workgroup per cell, one thread per
+// occupant): the same list as launch_ab_build(false, ...).
+void launch_ab_build_cells(const double *x, const double *y, const double *z, const int32_t *cs,
+                           int npad, int G, double L, double rn2, int mcap, int32_t *W,
+                           int32_t *m, int32_t *overflow, hipStream_t s);
 // Zero device memory with a kernel (bytes a multiple of 4).
 void launch_ab_zero(void *p, size_t bytes, hipStream_t s);
 // The A/B forces in the caller's order (out: n x 3 doubles) and the summed

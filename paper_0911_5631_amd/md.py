@@ -237,19 +237,36 @@ class System:
                                  C.byref(n)), "md_get_pairs")
         return pi[:n.value], pj[:n.value]
 
-    def newton3_ab(self, half: bool, reps: int = 1, noalloc: bool = False) -> Dict[str, object]:
-        """Full-list vs half-list (Newton's third law, atomics) force phase at
-        the held state: forces (original order), mean build and force kernel
-        times (ms), list entries.  noalloc: the entry point that allocates
-        no device memory (md_newton3_ab_noalloc)."""
+    def newton3_ab(self, variant="full", reps: int = 1, noalloc: bool = False) -> Dict[str, object]:
+        """Neighbour-list A/B at the held state: variant "full" (one thread
+        per atom), "half" (Newton's third law, reactions by atomics) or
+        "cells" (the cell-centric build; a bool selects half / full):
+        forces (original order), mean build and force kernel times (ms), list
+        entries.  noalloc: the entry point that allocates no device memory
+        (md_newton3_ab_noalloc)."""
+        if isinstance(variant, bool):
+            variant = "half" if variant else "full"
         f = np.empty((self.n, 3))
         b = C.c_double()
         t = C.c_double()
         k = C.c_int64()
         fn = lib().md_newton3_ab_noalloc if noalloc else lib().md_newton3_ab
-        check(fn(self._h, 1 if half else 0, int(reps), _dptr(f), C.byref(b), C.byref(t),
+        check(fn(self._h, L.AB_VARIANTS[variant], int(reps), _dptr(f), C.byref(b), C.byref(t),
                  C.byref(k)), "md_newton3_ab_noalloc" if noalloc else "md_newton3_ab")
         return {"force": f, "build_ms": b.value, "force_ms": t.value, "n_entries": k.value}
+
+    def ab_pairs(self, variant: str = "full") -> Tuple[np.ndarray, np.ndarray]:
+        """The A/B list of ``variant`` built at the held state, as (i, j)
+        original indices (md_ab_pairs)."""
+        n = C.c_int64()
+        v = L.AB_VARIANTS[variant]
+        check(lib().md_ab_pairs(self._h, v, 0, None, None, C.byref(n)), "md_ab_pairs")
+        cap = n.value
+        pi = np.empty(max(cap, 1), dtype=np.int32)
+        pj = np.empty(max(cap, 1), dtype=np.int32)
+        check(lib().md_ab_pairs(self._h, v, cap, pi.ctypes.data_as(_I32), pj.ctypes.data_as(_I32),
+                                C.byref(n)), "md_ab_pairs")
+        return pi[:n.value], pj[:n.value]
 
     # -- measurement ---------------------------------------------------------
     def profile(self, enable: bool) -> None:
