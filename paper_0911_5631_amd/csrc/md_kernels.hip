@@ -435,6 +435,8 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
   int64_t k = 0;
   bool skip = true, rebuild = false, unbinned = false;
   double d1 = 0.0;
+  // the atoms in a replica's tiles before tile run_upto (see below)
+  int run_rep = -1, run_upto = 0, run_pre = 0;
   for (int u = xcd_block(blockIdx.x, gridDim.x); u < nunits; u += gridDim.x) {
     const int t = u / nsp, sp = u - t * nsp;
     const int r = cview(T.ctile_rep)[t];
@@ -500,13 +502,21 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     const int lt = t - S.ctile_off;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 
-    // atoms in the earlier tiles
+    // atoms in the earlier tiles: a workgroup takes its units in increasing
+    // order, so the sum kept from its previous unit of the same replica only
+    // grows by the tiles in between (about the grid's size; O(tiles) loads
+    // per workgroup instead of every earlier tile at every unit).  Eight
+    // loads in flight per thread: integer sums, so the grouping does not
+    // change the result.
     const auto TC = gp((const int32_t *)S.tcnt[set]);
-    // (eight independent loads in flight per thread: integer sums, so the
-    // grouping does not change the result)
+    if (run_rep != r || run_upto > lt) {
+      run_rep = r;
+      run_upto = 0;
+      run_pre = 0;
+    }
     int pre = 0;
     {
-      int q = threadIdx.x;
+      int q = run_upto + (int)threadIdx.x;
       for (; q + 7 * TILE < lt; q += 8 * TILE) {
         int p8[8];
 #pragma unroll
@@ -530,7 +540,9 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     if (l == 63) s_wsum[w] = incl;
     const int wmax = wave_max_i(cnt);
     __syncthreads();
-    int before = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+    run_pre += ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+    run_upto = lt;
+    int before = run_pre;
     for (int q = 0; q < w; ++q) before += s_wsum[q];
     const int base = before + incl - cnt;
     if (sp == 0) {
