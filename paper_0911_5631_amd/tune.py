@@ -90,16 +90,25 @@ def store(path: Optional[str], key: str, entry: Dict) -> None:
 
 def autotune(batch, candidates: Iterable[Mapping] = DEFAULT_CANDIDATES, runs: int = 2,
              cache_path: Optional[str] = None, key: Optional[str] = None,
-             clock=None) -> Dict:
+             clock=None, warm_runs: int = 0) -> Dict:
     """Time ``runs`` runs of ``batch`` per candidate (after one untimed run
     that captures the candidate's graph), score each by atom-steps advanced
     per second, configure the batch with the best and return the trials.
+    ``warm_runs`` untimed runs at the batch's configuration come first, so
+    that no candidate is timed over the systems' first steps (from a lattice
+    start they rebuild later than they will afterwards).
 
     ``batch`` offers configure(**knobs), run(), poll() (synchronises) and
     progress() -> (atom-steps done, systems running, fewest steps left)."""
     clock = clock or time.perf_counter
     trials: List[Dict] = []
     _, running, left = batch.progress()
+    for _ in range(warm_runs):
+        if running == 0 or left <= 64:
+            break
+        batch.run()
+        batch.poll()
+        _, running, left = batch.progress()
     budget = left - 1          # steps every running system can still take safely
     for cand in candidates:
         c = _cfg(cand)
@@ -135,7 +144,7 @@ def autotune(batch, candidates: Iterable[Mapping] = DEFAULT_CANDIDATES, runs: in
 
 
 def autotune_system(system, n_atoms: int, candidates: Iterable[Mapping] = SINGLE_CANDIDATES,
-                    steps: int = 256, cache_path: Optional[str] = None,
+                    steps: int = 512, cache_path: Optional[str] = None,
                     key: Optional[str] = None, clock=None) -> Dict:
     """The same for one system: each candidate advances it ``steps`` real
     steps (after one untimed replay that warms the new graphs), timed to the

@@ -117,3 +117,15 @@ def test_cache_roundtrip(tmp_path):
     used = tune.apply_cached(b2, path, key)
     assert used == {k: out["best"][k] for k in tune.KNOBS}
     assert tune.apply_cached(b2, path, "gfx950/batch/3") is None
+
+
+def test_warm_runs_come_first_and_are_not_timed():
+    clock = Clock()
+    b = SimBatch(clock, [4000, 8000], [100000, 100000], grid_cost)
+    b.configure(64, 2048, 2048, 1, 1)
+    out = tune.autotune(b, runs=2, warm_runs=3, clock=clock)
+    runs = [e for e in b.log if e[0] == "run"]
+    assert runs[:3] == [("run", 64, 2048, 2048, 1, 1)] * 3     # at the batch's own config
+    first = tune._cfg(tune.DEFAULT_CANDIDATES[0])
+    assert b.log.index(("configure",) + tuple(first[k] for k in tune.KNOBS)) > 3
+    assert all("atom_steps_per_s" in t for t in out["trials"])
