@@ -120,7 +120,7 @@ def batched(n_replicas: int, steps: int, n_solo: int, solo_steps: int,
     cfg = TU.apply_cached(b, tune_cache, key)
     tuned = None
     if cfg is None:
-        tuned = TU.autotune(b, runs=3, warm_runs=2, cache_path=tune_cache, key=key)
+        tuned = TU.autotune(b, runs=3, warm_runs=2, trial_steps=192, cache_path=tune_cache, key=key)
         cfg = tuned["in_use"]
     done = 0
     while done < n_replicas:

@@ -90,13 +90,16 @@ def store(path: Optional[str], key: str, entry: Dict) -> None:
 
 def autotune(batch, candidates: Iterable[Mapping] = DEFAULT_CANDIDATES, runs: int = 2,
              cache_path: Optional[str] = None, key: Optional[str] = None,
-             clock=None, warm_runs: int = 0) -> Dict:
+             clock=None, warm_runs: int = 0, trial_steps: int = 0) -> Dict:
     """Time ``runs`` runs of ``batch`` per candidate (after one untimed run
     that captures the candidate's graph), score each by atom-steps advanced
     per second, configure the batch with the best and return the trials.
     ``warm_runs`` untimed runs at the batch's configuration come first, so
     that no candidate is timed over the systems' first steps (from a lattice
-    start they rebuild later than they will afterwards).
+    start they rebuild later than they will afterwards).  With
+    ``trial_steps`` every candidate is timed over at least that many steps
+    (more runs for shorter replays), so that candidates with short replays
+    are not scored over a window that happens to hold fewer rebuilds.
 
     ``batch`` offers configure(**knobs), run(), poll() (synchronises) and
     progress() -> (atom-steps done, systems running, fewest steps left)."""
@@ -113,7 +116,8 @@ def autotune(batch, candidates: Iterable[Mapping] = DEFAULT_CANDIDATES, runs: in
     for cand in candidates:
         c = _cfg(cand)
         spr = c["steps_per_run"] or 64
-        if running == 0 or (1 + runs) * spr > budget:
+        n_runs = max(runs, -(-int(trial_steps) // spr))
+        if running == 0 or (1 + n_runs) * spr > budget:
             trials.append({**c, "skipped": "a trial could finish a system"})
             continue
         batch.configure(**c)
@@ -121,17 +125,17 @@ def autotune(batch, candidates: Iterable[Mapping] = DEFAULT_CANDIDATES, runs: in
         batch.poll()
         a0, k0, _ = batch.progress()
         t0 = clock()
-        for _ in range(runs):
+        for _ in range(n_runs):
             batch.run()
         batch.poll()
         el = clock() - t0
-        a1, k1, left1 = batch.progress()
-        budget -= (1 + runs) * spr
+        a1, k1, _ = batch.progress()
+        budget -= (1 + n_runs) * spr
         if k1 != k0:
             trials.append({**c, "skipped": "the mix changed during the trial"})
             continue
         trials.append({**c, "atom_steps_per_s": (a1 - a0) / el if el > 0 else 0.0,
-                       "seconds": el})
+                       "seconds": el, "steps": n_runs * spr})
     scored = [t for t in trials if "atom_steps_per_s" in t]
     if not scored:
         return {"best": None, "trials": trials}

@@ -129,3 +129,16 @@ def test_warm_runs_come_first_and_are_not_timed():
     first = tune._cfg(tune.DEFAULT_CANDIDATES[0])
     assert b.log.index(("configure",) + tuple(first[k] for k in tune.KNOBS)) > 3
     assert all("atom_steps_per_s" in t for t in out["trials"])
+
+
+def test_trial_steps_equalise_the_timed_window():
+    clock = Clock()
+    b = SimBatch(clock, [4000, 8000], [100000, 100000], grid_cost)
+    out = tune.autotune(b, runs=2, trial_steps=192, clock=clock)
+    for tr in out["trials"]:
+        assert tr["steps"] == max(2 * tr["steps_per_run"], 192)
+    # spr 16: one capture run and twelve timed runs
+    first = tune._cfg(tune.DEFAULT_CANDIDATES[0])
+    cfg = tuple(first[k] for k in tune.KNOBS)
+    k = b.log.index(("configure",) + cfg)
+    assert b.log[k + 1:k + 14] == [("run",) + cfg] * 13 and b.log[k + 14][0] == "configure"
