@@ -122,6 +122,14 @@ typedef struct {
                           max(16, 2 x the mean occupancy + 8, rounded up to 8)
                           (grown on need) */
     uint32_t flags;    /* MD_EVEN_CELLS | MD_TRACE_PROPS | MD_NO_REORDER */
+    int32_t reorder_interval; /* N_R of Sec. 5.1 and Table 7: a rebuild reorders the
+                          atoms only when at least N_R steps have passed since the
+                          last reordering (the reordering is done when the next
+                          rebuild falls due); a rebuild that does not reorder
+                          works like one under MD_NO_REORDER.  0 = every rebuild
+                          (the default); < 0 invalid.  Like MD_NO_REORDER it
+                          changes the summation order, not the pairs.  Not with
+                          md_newton3_ab (MD_ERR_STATE) */
 } md_params;
 
 typedef struct {

@@ -54,7 +54,8 @@ class MDError(RuntimeError):
 class md_params(C.Structure):
     _fields_ = [("n_atoms", C.c_int64), ("box", C.c_double), ("r_cut", C.c_double),
                 ("shell", C.c_double), ("dt", C.c_double), ("precision", C.c_int32),
-                ("nebr_cap", C.c_int32), ("cell_cap", C.c_int32), ("flags", C.c_uint32)]
+                ("nebr_cap", C.c_int32), ("cell_cap", C.c_int32), ("flags", C.c_uint32),
+                ("reorder_interval", C.c_int32)]
 
 
 class md_props_t(C.Structure):

@@ -80,6 +80,9 @@ enum : int32_t {
 // step k-2, would fire at step k.
 constexpr double BIN_AHEAD = 1.5;
 
+// CtlDev::rb_ring values of a rebuilding step.
+enum : int32_t { RB_NONE = 0, RB_REORDER = 1, RB_PERM = 2 };
+
 // Modes of the step kernel (and of the sort kernel: MODE_STEP or not).
 enum : int32_t {
   MODE_STEP = 0,    // forces (c) + (d) + (e) [+ (a) of the next step and its binning]
@@ -129,6 +132,8 @@ struct SlotDev {
   int32_t nsp;       // species of a mixture (0: one species, the r_c / ushift above)
   int32_t noreo;     // MD_NO_REORDER: a sort finds the cell order (perm, cs) and the
                      // cells, wraps in place and moves nothing
+  int32_t nr;        // reorder interval N_R in steps (0: every rebuild reorders); a
+                     // rebuild that does not reorder works like one under noreo
 };
 
 // Per-replica mutable control block.  Written by the host between launches,
@@ -141,12 +146,16 @@ struct CtlDev {
   int64_t force_step;  // step whose binning is a rebuild regardless of the rule
   int64_t err_step;    // first step that could not be evaluated
   int64_t bins_step;   // step whose positions the host binned after ERR_UNBINNED (-1: none)
+  int64_t reo_ring[3]; // step of the last reordering as of step k, slot k % 3
   int64_t n_rebuilds;  // rebuilds by the displacement rule
   uint64_t vmax_ring[3];  // max v(k)^2 of ring entry k % 3, gathered by k_props (host view)
   double disp_ring[3];    // accumulated displacement after step k, slot k % 3
   int32_t clean;       // 1: r(done), v(done), F(done) are held; 0: drifted to r(done+1)
   int32_t var_ring[3]; // descriptor variant holding state k, slot k % 3
-  int32_t rb_ring[3];  // 1 if step k rebuilds (decided by k_sort of step k), slot k % 3
+  int32_t rb_ring[3];  // step k rebuilds (decided by k_sort of step k), slot k % 3:
+                       // RB_REORDER into the other variant, RB_PERM in place
+  int32_t ord_ring[3]; // 1 if the storage of state k is not the cell order of the last
+                       // sort (it rebuilt without reordering since), slot k % 3
   int32_t err;         // latched ERR_* bits
   int32_t max_h;       // largest cell occupancy seen by a sort
   int32_t pad1;

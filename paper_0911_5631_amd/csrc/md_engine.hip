@@ -56,6 +56,7 @@ struct Geometry {
   int64_t n;
   int G, ncell, ntiles, nctiles, npad, hcap, mcap, cpt;
   bool cell_only, fp64, trace, noreo;
+  int nr;  // reorder interval in steps (0: every rebuild)
   double L, rc, shell, rn;
 };
 
@@ -68,7 +69,7 @@ md_status geometry(const md_params *p, Geometry *g) {
       !std::isfinite(p->shell))
     return MD_ERR_INVALID_ARG;
   if (p->precision != MD_FORCE_FP32 && p->precision != MD_FORCE_FP64) return MD_ERR_INVALID_ARG;
-  if (p->nebr_cap < 0 || p->cell_cap < 0 ||
+  if (p->nebr_cap < 0 || p->cell_cap < 0 || p->reorder_interval < 0 ||
       (p->flags & ~(MD_EVEN_CELLS | MD_TRACE_PROPS | MD_NO_REORDER)))
     return MD_ERR_INVALID_ARG;
   g->n = p->n_atoms;
@@ -80,6 +81,7 @@ md_status geometry(const md_params *p, Geometry *g) {
   g->fp64 = p->precision == MD_FORCE_FP64;
   g->trace = (p->flags & MD_TRACE_PROPS) != 0;
   g->noreo = (p->flags & MD_NO_REORDER) != 0;
+  g->nr = g->noreo ? 0 : p->reorder_interval;
   const double q = std::floor(g->L / g->rn);
   if (q < 3) return MD_ERR_BOX_TOO_SMALL;
   if (q > 1290) return MD_ERR_INVALID_ARG;  // G^3 must fit int32 cell indices
@@ -152,7 +154,7 @@ Layout layout(const Geometry &g) {
     b += round_up((size_t)TRACE_RING * TRACE_W * 8, 256);
   }
   l.perm = 0;
-  if (g.noreo) {  // MD_NO_REORDER: the cell-order permutation of the last sort
+  if (g.noreo || g.nr > 0) {  // the cell-order permutation of a sort that does not reorder
     l.perm = b;
     b += round_up((size_t)g.npad * 4, 256);
   }
@@ -425,8 +427,9 @@ void describe(Replica *r) {
   d.vring = (unsigned long long *)(b + l.vring);
   d.tpart = g.trace ? (double *)(b + l.tpart) : nullptr;
   d.trace = g.trace ? (double *)(b + l.trace) : nullptr;
-  d.perm = g.noreo ? (int32_t *)(b + l.perm) : nullptr;
+  d.perm = g.noreo || g.nr > 0 ? (int32_t *)(b + l.perm) : nullptr;
   d.noreo = g.noreo ? 1 : 0;
+  d.nr = g.nr;
   d.W = (int32_t *)r->wmat;
   d.L = g.L;
   d.halfL = 0.5 * g.L;
@@ -703,7 +706,10 @@ void reset_ctl(CtlDev &c, int64_t step, int variant, int64_t n_rebuilds, int max
   c.bins_step = -1;
   c.n_rebuilds = n_rebuilds;
   c.clean = 1;
-  for (int q = 0; q < 3; ++q) c.var_ring[q] = variant;
+  for (int q = 0; q < 3; ++q) {
+    c.var_ring[q] = variant;
+    c.reo_ring[q] = step;  // a clean state is (re)sorted by the host in cell order
+  }
   c.max_h = max_h;
 }
 
@@ -1612,7 +1618,7 @@ md_status md_newton3_ab(md_system *s, int32_t variant, int32_t reps, double *for
     return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
   Replica *r = e->rep[0];
-  if (r->g.cell_only || r->nsp > 0 || r->g.noreo) return MD_ERR_STATE;
+  if (r->g.cell_only || r->nsp > 0 || r->g.noreo || r->g.nr > 0) return MD_ERR_STATE;
   Visit v(e);
   if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
@@ -1634,7 +1640,7 @@ md_status md_ab_pairs(md_system *s, int32_t variant, int64_t cap, int32_t *pi, i
     return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
   Replica *r = e->rep[0];
-  if (r->g.cell_only || r->nsp > 0 || r->g.noreo) return MD_ERR_STATE;
+  if (r->g.cell_only || r->nsp > 0 || r->g.noreo || r->g.nr > 0) return MD_ERR_STATE;
   Visit v(e);
   if ((st = v.enter()) != MD_OK) return st;
   if ((st = require_clean(e)) != MD_OK) return st;
@@ -1660,7 +1666,7 @@ md_status md_newton3_ab_noalloc(md_system *s, int32_t variant, int32_t reps, dou
     return MD_ERR_INVALID_ARG;
   Engine *e = s->e;
   Replica *r = e->rep[0];
-  if (r->g.cell_only || r->nsp > 0 || r->g.noreo) return MD_ERR_STATE;
+  if (r->g.cell_only || r->nsp > 0 || r->g.noreo || r->g.nr > 0) return MD_ERR_STATE;
   const AbLayout l = ab_layout(r->g);
   if (l.total > (size_t)MD_AB_SCRATCH_BYTES) return MD_ERR_OOM;  // beyond the static array
   void *base = scratch_ptr(e);
@@ -1712,7 +1718,8 @@ md_status md_get_bins(md_system *s, int32_t *order, int32_t *cell_start) {
   const SlotDev &d = r->dev[held_variant(e->h_ctl[0])];
   hipError_t err = hipSuccess;
   const int64_t n = r->g.n;
-  if (order && r->g.noreo) {
+  const CtlDev &hc = e->h_ctl[0];
+  if (order && (r->g.noreo || hc.ord_ring[((hc.done % 3) + 3) % 3] != 0)) {
     // no reordering: cell order is perm over the (unmoved) storage
     std::vector<int32_t> perm(n), id(n);
     err = hipMemcpyAsync(perm.data(), d.perm, (size_t)n * 4, hipMemcpyDeviceToHost, e->work);

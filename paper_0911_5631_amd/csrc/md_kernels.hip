@@ -433,7 +433,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
   // once for a run of consecutive cell tiles of one replica
   int rc = -1, var = 0;
   int64_t k = 0;
-  bool skip = true, rebuild = false, unbinned = false;
+  bool skip = true, rebuild = false, unbinned = false, reo = true;
   double d1 = 0.0;
   // the atoms in a replica's tiles before tile run_upto (see below)
   int run_rep = -1, run_upto = 0, run_pre = 0;
@@ -455,6 +455,9 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
         d1 = 0.0;
         if (!S0.cell_only) rebuild = rebuild_at(S0, C, k, &d1);
         unbinned = rebuild && !bins_due(S0, C, k) && k != C.bins_step;
+        // reorder at this rebuild, or keep the storage order (Table 7: the
+        // reordering is done at the first rebuild N_R steps after the last)
+        reo = !S0.noreo && (S0.nr <= 0 || k - C.reo_ring[mod3(k - 1)] >= S0.nr);
       } else {
         if (!C.clean) continue;
         k = C.done;
@@ -462,6 +465,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
         var = C.var_ring[mod3(k)];
         rebuild = true;
         unbinned = false;
+        reo = !S0.noreo;  // a sort of the held state reorders (k_flip records it)
       }
       skip = false;
     }
@@ -482,7 +486,8 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
         if (unbinned) {
           latch_error(C, ERR_UNBINNED, k);
         } else {
-          C.rb_ring[mod3(k)] = rebuild ? 1 : 0;
+          C.rb_ring[mod3(k)] = rebuild ? (reo ? RB_REORDER : RB_PERM) : RB_NONE;
+          C.reo_ring[mod3(k)] = rebuild && reo ? k : C.reo_ring[mod3(k - 1)];
           if (!S0.cell_only) {
             C.disp_ring[mod3(k - 1)] = d1;
             if (rebuild && k != C.force_step) C.n_rebuilds += 1;
@@ -554,7 +559,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
     const int n = S.n;
     const double L = S.L, halfL = S.halfL;
     const bool mixsp = S.nsp > 0;  // a mixture: the species move with the atoms
-    const bool noreo = S.noreo != 0;
+    const bool noreo = !reo;
     auto move = [&](int a, int cc, int p) {
       if (p >= n || a < 0 || a >= n) return;  // inconsistent counts: never expected
       if (noreo) {
@@ -681,6 +686,8 @@ __global__ void k_flip(Tables T, int only) {
   const int64_t k = C.done;
   if (C.err != 0 && C.err_step <= k) return;
   C.var_ring[mod3(k)] ^= 1;
+  C.ord_ring[mod3(k)] = 0;  // the held state is in cell order again
+  C.reo_ring[mod3(k)] = k;
 }
 
 // ---------------------------------------------------------------------------
@@ -1064,7 +1071,8 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
                                                const double *sz, double xi, double yi,
                                                double zi, bool build, bool force, bool energy,
                                                Acc<R> &a, const int8_t *ssp, gcint SP, int spi,
-                                               const PairTab *tab, bool global_only = false) {
+                                               const PairTab *tab, bool unord,
+                                               bool global_only = false) {
   const int G = S.G;
   const double L = S.L, rn2 = S.rn2, rc2 = S.rc2;
   const R ushift = (R)S.ushift;
@@ -1082,7 +1090,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   // window (the usual case: one code path, the reads of four candidates in
   // flight together), else each lane reads where its piece lives
   // without reordering, position j of cell order is the atom stored at perm[j]
-  const bool noreo = S.noreo != 0;
+  const bool noreo = unord;
   const gcint PERM = gp((const int32_t *)S.perm);
   auto candidates = [&](auto from_lds, int lo, int hi, int delta, uint32_t code, double bx,
                         double by, double bz) {
@@ -1233,6 +1241,20 @@ __device__ __forceinline__ void list_pair(Acc<R> &a, bool ok, uint32_t e, double
   }
 }
 
+// Whether the storage of the state that step k (or a host evaluation at
+// the held state k) works on is not the cell order of the last sort: always
+// without reordering, else after a rebuild that kept the storage order
+// (CtlDev::rb_ring) and until the next reordering (CtlDev::ord_ring).  The
+// words are read through the constant view (written by earlier launches), so
+// the test can be made again wherever it is needed instead of held.
+template <class Ctl>
+__device__ __forceinline__ bool unordered(SlotC &S, const Ctl &C, int64_t k, int mode) {
+  if (S.noreo) return true;
+  if (mode != MODE_STEP) return C.ord_ring[mod3(k)] != 0;
+  const int rb = C.rb_ring[mod3(k)];
+  return rb != RB_NONE ? rb == RB_PERM : C.ord_ring[mod3(k - 1)] != 0;
+}
+
 // ACC: the steps of a block, which sum their properties and add them to the
 // block sums.  MIX: a mixture (species staged with the window, pair
 // parameters in LDS).
@@ -1295,13 +1317,15 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
       ((double *)&stab)[threadIdx.x] = gp((const double *)S.tab)[threadIdx.x];
     if (act) spi = SP[i];
   }
-  if (cells && S.noreo) {
+  if (cells && unordered(S, *cview(&C), k, mode)) {
     // no reordering: the tile's atoms are not a run of cells, so there is no
-    // window; candidates are read from global memory through perm
+    // window; candidates are read from global memory through perm, and the
+    // list steps until the next sort stage nothing
     if (threadIdx.x == 0) {
       win.wt[0] = -1;
       win.whole = 0;
       win.rf = 0;
+      gp(S.win)[(size_t)lt * WSTRIDE] = -1;
     }
     __syncthreads();
   } else if (cells) {
@@ -1319,7 +1343,8 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
   if (act) {
     if (cells) {
       m = traverse_sorted<R, MIX>(S, i, ci, X, Y, Z, win, sx, sy, sz, xi, yi, zi, build, force,
-                                  mode != MODE_STEP || last || ACC, a, ssp, SP, spi, tab);
+                                  mode != MODE_STEP || last || ACC, a, ssp, SP, spi, tab,
+                                  unordered(S, *cview(&C), k, mode));
       if (build) gp(S.m)[i] = m;
     } else if (list) {
       if (m <= S.mcap) {
@@ -1382,7 +1407,7 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
         // neither moved more than delta/2), reading them from global memory
         traverse_sorted<R, MIX>(S, i, gp(S.cell)[i], X, Y, Z, win, sx, sy, sz, xi, yi, zi,
                                 false, true, mode != MODE_STEP || last || ACC, a, ssp, SP, spi,
-                                tab, true);
+                                tab, unordered(S, *cview(&C), k, mode), true);
       }
     }
   }
@@ -1553,10 +1578,12 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
         if (k > C.target) continue;
         last = k == C.target;
         var = C.var_ring[mod3(k - 1)];
-        // k_sort of this step decided, and if so gathered r(k) into the other variant
-        cells = C.rb_ring[mod3(k)] != 0;
+        // k_sort of this step decided, and if so gathered r(k) into the other
+        // variant (or, without reordering, found the cell order in place)
+        const int rb = C.rb_ring[mod3(k)];
+        cells = rb != RB_NONE;
         build = cells && !S0.cell_only;
-        if (cells && !S0.noreo) var ^= 1;
+        if (rb == RB_REORDER) var ^= 1;
         // r(k+1) is binned here if a sort at step k+1 may need its rows
         bin_next = !last && bins_due(S0, C, k + 1);
       } else {
@@ -1575,9 +1602,13 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
     CtlDev &C = T.ctl[r];
     SlotC &S = slot(T, 2 * r + var);
     const int lt = t - S.tile_off;
+    if (mode == MODE_STEP && lt == 0 && threadIdx.x == 0) {
+      // the one writer of these ring slots in this launch (nobody reads them
+      // before the next launch)
+      C.var_ring[mod3(k)] = var;
+      C.ord_ring[mod3(k)] = unordered(S, *cview(&C), k, mode) ? 1 : 0;
+    }
     step_tile<R, ACC, MIX>(S, C, lt, k, mode, cells, build, last, bin_next);
-    if (mode == MODE_STEP && lt == 0 && threadIdx.x == 0)
-      C.var_ring[mod3(k)] = var;  // the one writer of this ring slot in this launch
     if (mode == MODE_STEP && lt == 0 && threadIdx.x < VSPREAD)
       S.vring[(mod3(k + 1) * VSPREAD + threadIdx.x) * 16] = 0ull;
   }

@@ -147,3 +147,117 @@ def test_no_reorder_fp32_trajectory_and_batch():
     bp, bv, bstep = b.get_state(slot)
     b.close()
     assert bstep == 60 and np.array_equal(bp, p) and np.array_equal(bv, v)
+
+
+# ---------------------------------------------------------------------------
+# the reorder interval N_R (Table 7): a rebuild reorders only when N_R steps
+# have passed since the last reordering, and otherwise works like one under
+# MD_NO_REORDER
+# ---------------------------------------------------------------------------
+
+def _first_rebuilds(pos, vel, L, shell, steps):
+    sim = O.Sim(pos, vel, L, shell=shell)
+    tr = sim.run(steps)
+    sim.close()
+    return [k + 1 for k in range(steps) if tr[k, 5]]
+
+
+def test_reorder_interval_bins_at_a_rebuild_that_keeps_the_order():
+    """N_R = 10^4: the creation sort reorders, the first rebuild in a step does
+    not: its cell order is the stable sort by cell of the storage order left
+    by the creation sort."""
+    pos, L = I.fcc_lattice(10, 0.8)
+    vel = I.random_velocities(len(pos), 1.0, 41)
+    pos, vel = I.shuffled(pos, vel, 42)
+    G = O.cells_per_edge(L, RC + 0.4)
+    k1 = _first_rebuilds(pos, vel, L, 0.4, 200)[0]
+    s = _system(pos, vel, L, shell=0.4, precision="fp64", reorder_interval=10000)
+    storage0, _ = s.bins()                 # original ids in storage order after creation
+    s.step(k1)
+    assert s.props()["n_rebuilds"] == 1
+    sim = O.Sim(pos, vel, L, shell=0.4)
+    sim.run(k1)
+    r1, _, _, _ = sim.state()
+    sim.close()
+    cells1 = O.cell_ids(r1, L, G)
+    expect = storage0[np.argsort(cells1[storage0], kind="stable")]
+    _, _, cs, _ = O.layers_reorder(cells1, G)
+    got_order, got_cs = s.bins()
+    assert np.array_equal(got_cs, cs) and np.array_equal(got_order, expect)
+    # the pair set of that rebuild is the oracle's
+    rpi, rpj, _ = O.pairs_cells(r1, L, G, RC + 0.4)
+    pi, pj = s.pairs()
+    assert np.array_equal(O.pair_set(pi, pj), O.pair_set(rpi, rpj))
+    s.close()
+
+
+@pytest.mark.parametrize("nr", [30, 75])
+def test_reorder_interval_fp64_trajectory(nr):
+    """FP64 over 300 steps with rebuilds that reorder and rebuilds that do
+    not: the oracle's trajectory to summation order, its rebuild count, and
+    the reordering rebuilds where N_R says."""
+    pos, L = I.fcc_lattice(10, 0.8)
+    vel = I.random_velocities(len(pos), 1.0, 51)
+    n = len(pos)
+    rb = _first_rebuilds(pos, vel, L, 0.4, 300)
+    assert len(rb) >= 6
+    s = _system(pos, vel, L, shell=0.4, precision="fp64", reorder_interval=nr)
+    sim = O.Sim(pos, vel, L, shell=0.4)
+    done = 0
+    for k in rb:                      # calls that end at every rebuild step
+        s.step(k - done)
+        done = k
+    s.step(300 - done)
+    tr = sim.run(300)
+    p, v, f, step = s.get_state()
+    rp, rv, rf, _ = sim.state()
+    pr = s.props()
+    sim.close()
+    s.close()
+    assert step == 300 and pr["n_rebuilds"] == len(rb)
+    assert np.abs(min_image(p - rp, L)).max() < 1e-9
+    assert np.abs(v - rv).max() < 1e-8
+    assert force_error(f, rf) < 1e-9
+    assert abs(pr["pe"] - tr[-1, 1]) / n < 1e-10
+
+
+def test_reorder_interval_fp32_batch_equals_solo_and_oracle():
+    from paper_0911_5631_amd.md import Batch
+    pos, vel, L = _fluid(9, 61, amp=0.05)
+    n = len(pos)
+    s = _system(pos, vel, L, shell=0.4, reorder_interval=40)
+    s.step(150)
+    p, v, _, _ = s.get_state()
+    pr = s.props()
+    s.close()
+    sim = O.Sim(pos, vel, L, shell=0.4)
+    tr = sim.run(150)
+    rp, _, _, _ = sim.state()
+    sim.close()
+    assert pr["n_rebuilds"] == int(tr[:, 5].sum()) >= 3
+    assert np.abs(min_image(p - rp, L)).max() < 1e-6
+    assert abs(pr["pe"] - tr[-1, 1]) / n < 1e-5
+    other = I.fcc_system("other", 6, 0.8, 1.0, seed=7)
+    b = Batch(1 << 30, 2, 32)
+    b.admit(other.pos, other.vel, other.box, 150, shell=0.4)
+    slot = b.admit(pos, vel, L, 150, shell=0.4, reorder_interval=40)
+    for _ in range(20):
+        b.run()
+        if slot in b.poll():
+            break
+    bp, bv, bstep = b.get_state(slot)
+    b.close()
+    assert bstep == 150 and np.array_equal(bp, p) and np.array_equal(bv, v)
+
+
+def test_reorder_interval_refused_where_it_does_not_apply():
+    from paper_0911_5631_amd._lib import MDError
+    pos, vel, L = _fluid(7, 71)
+    with pytest.raises(MDError) as e:
+        _system(pos, vel, L, shell=0.4, reorder_interval=-1)
+    assert e.value.code == -1
+    s = _system(pos, vel, L, shell=0.4, reorder_interval=20)
+    with pytest.raises(MDError) as e:
+        s.newton3_ab()
+    assert e.value.code == -8
+    s.close()
