@@ -53,6 +53,9 @@ SINGLE_CANDIDATES = (
     {"steps_per_run": 64, "grid": 0, "sort_grid": 2048, "sort_split": 0, "tile_order": 2},
     {"steps_per_run": 64, "grid": 0, "sort_grid": 4096, "sort_split": 0, "tile_order": 2},
     {"steps_per_run": 32, "grid": 0, "sort_grid": 0, "sort_split": 0, "tile_order": 2},
+    {"steps_per_run": 64, "grid": 4096, "sort_grid": 0, "sort_split": 0, "tile_order": 2},
+    {"steps_per_run": 64, "grid": 8192, "sort_grid": 0, "sort_split": 0, "tile_order": 2},
+    {"steps_per_run": 64, "grid": 16384, "sort_grid": 0, "sort_split": 0, "tile_order": 2},
 )
 
 
