@@ -185,11 +185,14 @@ typedef struct {
     int32_t sort_split;    /* workgroups sharing one 256-cell tile of the sort,
                               1..32 (0: about 1024 atoms per workgroup for a
                               single system, 1 for a batch) */
-    int32_t tile_order;    /* MD_ORDER_PASSES: in each pass over the tiles the 8
-                              XCDs take consecutive runs of grid/8 tiles;
-                              MD_ORDER_SLABS (0 asks for it): each XCD walks its
-                              own eighth of the tiles, so a tile's neighbours in
-                              z are staged through the same L2 */
+    int32_t tile_order;    /* MD_ORDER_PASSES (0 asks for it in a batch): in each
+                              pass over the tiles the 8 XCDs take consecutive
+                              runs of grid/8 tiles, so work of uneven cost (the
+                              systems of a batch rebuild at different steps)
+                              spreads over every XCD; MD_ORDER_SLABS (0 asks for
+                              it for a single system): each XCD walks its own
+                              eighth of the tiles, so a tile's neighbours in z
+                              are staged through the same L2 */
 } md_launch_t;
 
 #define MD_ORDER_PASSES 1

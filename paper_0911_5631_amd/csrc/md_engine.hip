@@ -475,6 +475,15 @@ void describe(Replica *r) {
 }
 
 // Rebuild the tile tables and upload the descriptors of every slot (sync).
+// Tile order of the step kernel in use: the one asked for, else passes for
+// a batch (its systems rebuild at different steps, so the cost of the tiles
+// is uneven and is best spread over every XCD) and XCD slabs for a single
+// system (z-neighbour rows staged through the same L2).
+int tile_order(const Engine *e) {
+  if (e->order_req == MD_ORDER_PASSES || e->order_req == MD_ORDER_SLABS) return e->order_req;
+  return e->batch ? MD_ORDER_PASSES : MD_ORDER_SLABS;
+}
+
 md_status upload_tables(Engine *e) {
   hipError_t err = hipStreamSynchronize(e->work);
   if (err != hipSuccess) return e->fail("upload tables", err);
@@ -525,7 +534,7 @@ md_status upload_tables(Engine *e) {
   }
   if (e->split_req > 0) split = e->split_req;
   hdr[HDR_SPLIT] = split;
-  hdr[HDR_ORDER] = e->order_req == MD_ORDER_PASSES ? ORDER_PASSES : ORDER_SLABS;
+  hdr[HDR_ORDER] = tile_order(e) == MD_ORDER_PASSES ? ORDER_PASSES : ORDER_SLABS;
   for (int s = 0; s < e->max_slots; ++s) {
     Replica *r = e->rep[s];
     if (!r) {
@@ -1279,7 +1288,7 @@ md_status configure(Engine *e, md_launch_t *cfg) {
   cfg->grid = e->grid;
   cfg->sort_grid = e->cgrid;
   cfg->sort_split = e->split;
-  cfg->tile_order = e->order_req == MD_ORDER_PASSES ? MD_ORDER_PASSES : MD_ORDER_SLABS;
+  cfg->tile_order = tile_order(e);
   return MD_OK;
 }
 
