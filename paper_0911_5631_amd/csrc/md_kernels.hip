@@ -1167,6 +1167,73 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
     b[2] = CS[row + xe];
     b[3] = CS[row + xe + 1];
   };
+  // A wave with lanes at an x-edge of the box (cx = 0 or G-1) visits each
+  // row as one loop over the lane's two ranges, the wrapped cell and the
+  // row's own cells in x order (cell G-1 first when cx = 0, cell 0 last
+  // when cx = G-1: the order of separate visits, so the same list and the
+  // same sums), instead of three loops of which two run for a few lanes.
+  // Every candidate then takes its own window offset and x image shift.
+  const bool edge = wlo || whi;
+  const bool anyedge = __ballot(edge) != 0;
+  auto merged = [&](int loM, int hiM, int dM, int loW, int hiW, int dW, uint32_t cyz, double by,
+                    double bz) {
+    if (!edge) loW = hiW = 0;
+    const int loF = wlo ? loW : loM, hiF = wlo ? hiW : hiM;
+    const int loS = wlo ? loM : loW, hiS = wlo ? hiM : hiW;
+    const int lenF = hiF - loF, tot = lenF + (hiS - loS);
+    const double bw = wlo ? L : -L;
+    const uint32_t cw = cyz | ((wlo ? 1u : 3u) << J_BITS);
+    for (int k0 = 0; k0 < tot; k0 += 4) {
+      double xj[4], yj[4], zj[4];
+      int sj[4], js[4], jj[4];
+      bool isw[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = min(k0 + u, tot - 1);
+        const bool inF = k < lenF;
+        const int j = inF ? loF + k : loS + (k - lenF);
+        isw[u] = edge && inF == wlo;
+        const int d = isw[u] ? dW : dM;
+        jj[u] = j;
+        js[u] = j;
+        if (d != NOSLOT) {
+          xj[u] = sx[j + d];
+          yj[u] = sy[j + d];
+          zj[u] = sz[j + d];
+          if (MIX) sj[u] = ssp[j + d];
+        } else {
+          if (noreo) js[u] = PERM[j];
+          xj[u] = X[js[u]];
+          yj[u] = Y[js[u]];
+          zj[u] = Z[js[u]];
+          if (MIX) sj[u] = SP[js[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (k0 + u >= tot || js[u] == i) continue;
+        double dx = xi - xj[u], dy = yi - yj[u], dz = zi - zj[u];
+        dx = dx + (isw[u] ? bw : 0.0);
+        dy = dy + by;
+        dz = dz + bz;
+        const double s = (dx * dx + dy * dy) + dz * dz;
+        if (s < rn2) {
+          if (build) {
+            const int d = isw[u] ? dW : dM;
+            const uint32_t idx = d != NOSLOT ? (uint32_t)(jj[u] + d) : ((uint32_t)js[u] | GFLAG);
+            if (m < mcap) Wc[(size_t)m * np] = (int32_t)(idx | (isw[u] ? cw : cyz));
+            ++m;
+          }
+          if (MIX) {
+            const int kk = (spi * MAXSP + sj[u]) & (MAXSP * MAXSP - 1);
+            if (force && s < tab->rc2[kk]) pair_accum_mix<R>(a, dx, dy, dz, s, tab, kk, energy);
+          } else if (force && s < rc2) {
+            pair_accum<R>(a, dx, dy, dz, s, ushift, energy);
+          }
+        }
+      }
+    }
+  };
   int cur[4], nxt[4];
   bounds(0, cur);
 #pragma unroll 1
@@ -1186,9 +1253,10 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
       d0 = w.dl[e + 1];
       dg = w.dl[e + 2];
     }
-    range(wlo ? cur[2] : 0, wlo ? cur[3] : 0, dg, cyz | (1u << J_BITS), L, by, bz);
-    range(cur[0], cur[1], dm, cyz, 0.0, by, bz);
-    range(whi ? cur[2] : 0, whi ? cur[3] : 0, d0, cyz | (3u << J_BITS), -L, by, bz);
+    if (anyedge)
+      merged(cur[0], cur[1], dm, cur[2], cur[3], wlo ? dg : d0, cyz, by, bz);
+    else
+      range(cur[0], cur[1], dm, cyz, 0.0, by, bz);
 #pragma unroll
     for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
   }
