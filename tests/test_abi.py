@@ -66,3 +66,47 @@ def test_product_path_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct of include/md.h has the size and field offsets the
+    binding declares (compiled with the host C compiler from the header)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = [_lib.md_params, _lib.md_props_t, _lib.md_trace_t, _lib.md_block_t,
+               _lib.md_launch_t, _lib.md_allocator]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "md.h"', "int main(void) {"]
+    for st in structs:
+        t = st.__name__
+        lines.append(f'printf("{t} size %zu\\n", sizeof({t}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{t} {f} %zu\\n", offsetof({t}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n"):
+        if line:
+            t, f, v = line.split()
+            got[(t, f)] = int(v)
+    for st in structs:
+        t = st.__name__
+        assert got[(t, "size")] == C.sizeof(st), t
+        for f, _ in st._fields_:
+            assert got[(t, f)] == getattr(st, f).offset, (t, f)
+
+
+def test_reorder_interval_is_validated():
+    with pytest.raises(_lib.MDError) as e:
+        md_query_bytes(make_params(4000, 20.0, reorder_interval=-1))
+    assert e.value.code == -1
+    # a permutation array is kept when the storage order may lag the cell order
+    a = md_query_bytes(make_params(256000, 68.39903786706787))
+    b = md_query_bytes(make_params(256000, 68.39903786706787, reorder_interval=100))
+    assert b - a >= 4 * 256000
