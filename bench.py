@@ -530,8 +530,9 @@ def main() -> int:
                          "point for profilers), untimed")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs each system on a single MI355X "
-              "(multi-GPU sharding is not implemented); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: each system runs on a single MI355X "
+              "(sharding a system over several GPUs is not implemented); run with --gpus 1",
+              file=sys.stderr)
         return 2
 
     cpu_rep = None
