@@ -120,6 +120,34 @@ def test_binary_fp64_trajectory_matches_oracle():
     ref.close()
 
 
+@pytest.mark.parametrize("reorder_interval,reorder", [(40, True), (0, False)])
+def test_binary_fp64_trajectory_without_reordering(reorder_interval, reorder):
+    """The reorder interval and MD_NO_REORDER with a mixture: species stay
+    with their atoms through rebuilds that keep the storage order (their
+    candidates read through the cell-order permutation), and the trajectory
+    is the oracle's to summation order."""
+    pos, vel, L, sp = binary_fluid(13, 6, amp=0.08)
+    eps, sig, rc, sh = wca_binary()
+    n = len(pos)
+    s = _system(pos, vel, L, r_cut=rc.max(), shell=0.4, precision="fp64",
+                reorder_interval=reorder_interval, reorder=reorder)
+    s.set_species(sp, eps, sig, rc, sh)
+    ref = O.Sim(pos, vel, L, shell=0.4, rc=rc.max(), ushift=0.0)
+    ref.set_species(O.Mixture(sp, eps, sig, rc, sh))
+    s.step(150)
+    tr = ref.run(150)
+    p, v, _, step = s.get_state()
+    rp, rv, _, _ = ref.state()
+    pr = s.props()
+    s.close()
+    ref.close()
+    assert step == 150
+    assert np.abs(min_image(p - rp, L)).max() < 1e-9
+    assert np.abs(v - rv).max() < 1e-8
+    assert abs(pr["pe"] - tr[-1, 1]) / n < 1e-10
+    assert pr["n_rebuilds"] == int(tr[:, 5].sum()) and pr["n_rebuilds"] > 3
+
+
 def test_binary_fp32_trajectory_matches_oracle():
     pos, vel, L, sp = binary_fluid(15, 5, amp=0.08)
     eps, sig, rc, sh = wca_binary()
