@@ -103,6 +103,11 @@ typedef enum {
                              pair set and forces are those of the reordering
                              method (the summation order differs).  Not with
                              md_newton3_ab (MD_ERR_STATE) */
+#define MD_NO_WINDOW 8u   /* ablation: no LDS window; every candidate of a build
+                             and every neighbour of a list step is read from
+                             global memory (the analogue of the paper's run
+                             with the texture cache off, Sec. 5).  The same
+                             pairs in the same order: results bit-identical */
 
 typedef struct {
     int64_t n_atoms;   /* 1 <= N < 2^25 */
@@ -121,7 +126,7 @@ typedef struct {
     int32_t cell_cap;  /* initial per-cell layer capacity; 0 = from the density:
                           max(16, 2 x the mean occupancy + 8, rounded up to 8)
                           (grown on need) */
-    uint32_t flags;    /* MD_EVEN_CELLS | MD_TRACE_PROPS | MD_NO_REORDER */
+    uint32_t flags;    /* MD_EVEN_CELLS | MD_TRACE_PROPS | MD_NO_REORDER | MD_NO_WINDOW */
     int32_t reorder_interval; /* N_R of Sec. 5.1 and Table 7: a rebuild reorders the
                           atoms only when at least N_R steps have passed since the
                           last reordering (the reordering is done when the next

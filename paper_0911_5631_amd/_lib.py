@@ -16,6 +16,7 @@ MD_FORCE_FP64 = 1
 MD_EVEN_CELLS = 1
 MD_TRACE_PROPS = 2
 MD_NO_REORDER = 4
+MD_NO_WINDOW = 8
 AB_VARIANTS = {"full": 0, "half": 1, "cells": 2}
 
 STATUS = {

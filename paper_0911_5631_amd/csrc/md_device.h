@@ -134,6 +134,7 @@ struct SlotDev {
                      // cells, wraps in place and moves nothing
   int32_t nr;        // reorder interval N_R in steps (0: every rebuild reorders); a
                      // rebuild that does not reorder works like one under noreo
+  int32_t nowin;     // MD_NO_WINDOW: no LDS window (every read from global memory)
 };
 
 // Per-replica mutable control block.  Written by the host between launches,

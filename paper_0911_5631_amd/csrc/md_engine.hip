@@ -55,7 +55,7 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Geometry {
   int64_t n;
   int G, ncell, ntiles, nctiles, npad, hcap, mcap, cpt;
-  bool cell_only, fp64, trace, noreo;
+  bool cell_only, fp64, trace, noreo, nowin;
   int nr;  // reorder interval in steps (0: every rebuild)
   double L, rc, shell, rn;
 };
@@ -70,7 +70,7 @@ md_status geometry(const md_params *p, Geometry *g) {
     return MD_ERR_INVALID_ARG;
   if (p->precision != MD_FORCE_FP32 && p->precision != MD_FORCE_FP64) return MD_ERR_INVALID_ARG;
   if (p->nebr_cap < 0 || p->cell_cap < 0 || p->reorder_interval < 0 ||
-      (p->flags & ~(MD_EVEN_CELLS | MD_TRACE_PROPS | MD_NO_REORDER)))
+      (p->flags & ~(MD_EVEN_CELLS | MD_TRACE_PROPS | MD_NO_REORDER | MD_NO_WINDOW)))
     return MD_ERR_INVALID_ARG;
   g->n = p->n_atoms;
   g->L = p->box;
@@ -81,6 +81,7 @@ md_status geometry(const md_params *p, Geometry *g) {
   g->fp64 = p->precision == MD_FORCE_FP64;
   g->trace = (p->flags & MD_TRACE_PROPS) != 0;
   g->noreo = (p->flags & MD_NO_REORDER) != 0;
+  g->nowin = (p->flags & MD_NO_WINDOW) != 0;
   g->nr = g->noreo ? 0 : p->reorder_interval;
   const double q = std::floor(g->L / g->rn);
   if (q < 3) return MD_ERR_BOX_TOO_SMALL;
@@ -430,6 +431,7 @@ void describe(Replica *r) {
   d.perm = g.noreo || g.nr > 0 ? (int32_t *)(b + l.perm) : nullptr;
   d.noreo = g.noreo ? 1 : 0;
   d.nr = g.nr;
+  d.nowin = g.nowin ? 1 : 0;
   d.W = (int32_t *)r->wmat;
   d.L = g.L;
   d.halfL = 0.5 * g.L;

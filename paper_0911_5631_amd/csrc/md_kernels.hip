@@ -810,12 +810,13 @@ __device__ void make_window(SlotC &S, int lt, Window &w, int *scratch) {
     const auto CL = gp((const int32_t *)S.cell);
     const int c_f = CL[i_f], c_l = CL[i_l];
     const int rf = c_f / G, rl = c_l / G, ns = rl - rf + 1;
+    const bool whole = n <= WCAP && !S.nowin;
     if (lane == 0) {
       w.rf = rf;
-      w.whole = n <= WCAP;
+      w.whole = whole;
     }
-    if (n <= WCAP || ns * 9 > NROWS) {
-      if (lane == 0) s_np = n <= WCAP ? -2 : -1;  // whole system / no window
+    if (whole || ns * 9 > NROWS || S.nowin) {
+      if (lane == 0) s_np = whole ? -2 : -1;  // whole system / no window
     } else {
       if (lane < ns * 9) {
         const int sr = lane / 9, q = lane % 9;

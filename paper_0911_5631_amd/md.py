@@ -72,10 +72,10 @@ def make_params(n_atoms: int, box: float, *, r_cut: float = RC_SOFT_SPHERE, shel
                 dt: float = 0.005, precision: str = "fp32", nebr_cap: int = 0,
                 cell_cap: int = 0, even_cells: bool = False,
                 trace: bool = False, reorder: bool = True,
-                reorder_interval: int = 0) -> L.md_params:
+                reorder_interval: int = 0, window: bool = True) -> L.md_params:
     prec = {"fp32": L.MD_FORCE_FP32, "fp64": L.MD_FORCE_FP64}[precision]
     flags = ((L.MD_EVEN_CELLS if even_cells else 0) | (L.MD_TRACE_PROPS if trace else 0) |
-             (0 if reorder else L.MD_NO_REORDER))
+             (0 if reorder else L.MD_NO_REORDER) | (0 if window else L.MD_NO_WINDOW))
     return L.md_params(int(n_atoms), float(box), float(r_cut), float(shell), float(dt), prec,
                        int(nebr_cap), int(cell_cap), flags, int(reorder_interval))
 

@@ -261,3 +261,28 @@ def test_reorder_interval_refused_where_it_does_not_apply():
         s.newton3_ab()
     assert e.value.code == -8
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# MD_NO_WINDOW: the LDS window switched off (the analogue of the paper's
+# texture-cache experiment); the same candidates in the same order, so the
+# same lists and sums
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nc,precision", [(12, "fp32"), (7, "fp32"), (10, "fp64")])
+def test_no_window_is_bit_identical(nc, precision):
+    pos, vel, L = _fluid(nc, 81 + nc)
+    runs = []
+    for window in (True, False):
+        s = _system(pos, vel, L, shell=0.4, precision=precision, window=window)
+        s.step(250)
+        p, v, f, step = s.get_state()
+        pi, pj = s.pairs()
+        pr = s.props()
+        s.close()
+        runs.append((p, v, f, O.pair_set(pi, pj), pr))
+    (p0, v0, f0, ps0, pr0), (p1, v1, f1, ps1, pr1) = runs
+    assert pr0["n_rebuilds"] == pr1["n_rebuilds"] >= 3
+    assert np.array_equal(p0, p1) and np.array_equal(v0, v1) and np.array_equal(f0, f1)
+    assert np.array_equal(ps0, ps1)
+    assert pr0["pe"] == pr1["pe"] and pr0["virial"] == pr1["virial"]
