@@ -1004,54 +1004,47 @@ template <bool MIX>
 __device__ __forceinline__ void stage_window(const int *wt, gcdouble X, gcdouble Y, gcdouble Z,
                                              double *sx, double *sy, double *sz, gcint SP,
                                              int8_t *ssp) {
-  // the intervals fill slots 0 .. total-1 in order: thread t takes slots
-  // t, t + TILE, ... (at most SPT of them) and walks the interval table
-  // forward.  The source indices are found first; the loads then go out in
-  // two batches, each wholly issued before its LDS writes, so a thread waits
-  // for memory twice.
-  constexpr int SPT = (WCAP + TILE - 1) / TILE, B0 = (SPT + 1) / 2;
+  // The intervals fill slots 0 .. total-1 in order.  The coordinates go
+  // straight from global memory into LDS (loads that write LDS, not
+  // registers): wave w fills chunks of 32 slots c = w, w + 4, ..., lane l
+  // the low (l even) or high (l odd) word of slot 32c + l/2, whose source it
+  // finds by walking the interval table forward.  Nothing waits for the
+  // data here, so all of a wave's loads are in flight together; the barrier
+  // after the staging waits for them.
   const int nint = wt[0];
   if (nint <= 0) return;
   const int total = wt[3 * nint] + wt[3 * nint - 1];
-  int src[SPT];
+  typedef __attribute__((address_space(1))) const char *gcchar;
+  typedef __attribute__((address_space(3))) void *lvoid;
+  const int l = threadIdx.x & 63;
+  const int c0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nch = (total + 31) >> 5;
   int q = 0, end = wt[2];
-#pragma unroll
-  for (int u = 0; u < SPT; ++u) {
-    const int sl = threadIdx.x + u * TILE;
-    src[u] = -1;
+  for (int c = c0; c < nch; c += TILE / 64) {
+    const int sl = 32 * c + (l >> 1);
     if (sl < total) {
       while (sl >= end) {
         ++q;
         end = wt[3 * q + 3] + wt[3 * q + 2];
       }
-      src[u] = wt[3 * q + 1] + (sl - wt[3 * q + 3]);
+      const size_t off = (size_t)(wt[3 * q + 1] + (sl - wt[3 * q + 3])) * 8 + 4 * (l & 1);
+      __builtin_amdgcn_global_load_lds((gcchar)X + off, (lvoid)((char *)sx + 256 * c), 4, 0, 0);
+      __builtin_amdgcn_global_load_lds((gcchar)Y + off, (lvoid)((char *)sy + 256 * c), 4, 0, 0);
+      __builtin_amdgcn_global_load_lds((gcchar)Z + off, (lvoid)((char *)sz + 256 * c), 4, 0, 0);
     }
   }
-  auto batch = [&](auto first, auto count) {
-    constexpr int U0 = decltype(first)::value, NU = decltype(count)::value;
-    double bx[NU], by[NU], bz[NU];
-    int bs[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const int j = max(src[U0 + u], 0);  // a slot beyond the window reads atom 0, unstored
-      bx[u] = X[j];
-      by[u] = Y[j];
-      bz[u] = Z[j];
-      if (MIX) bs[u] = SP[j];
-    }
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      if (src[U0 + u] >= 0) {
-        const int sl = threadIdx.x + (U0 + u) * TILE;
-        sx[sl] = bx[u];
-        sy[sl] = by[u];
-        sz[sl] = bz[u];
-        if (MIX) ssp[sl] = (int8_t)bs[u];
+  if constexpr (MIX) {
+    // the species bytes through registers (after the coordinates' loads
+    // have gone out)
+    int qs = 0, es = wt[2];
+    for (int sl = threadIdx.x; sl < total; sl += TILE) {
+      while (sl >= es) {
+        ++qs;
+        es = wt[3 * qs + 3] + wt[3 * qs + 2];
       }
+      ssp[sl] = (int8_t)SP[wt[3 * qs + 1] + (sl - wt[3 * qs + 3])];
     }
-  };
-  batch(std::integral_constant<int, 0>{}, std::integral_constant<int, B0>{});
-  batch(std::integral_constant<int, B0>{}, std::integral_constant<int, SPT - B0>{});
+  }
 }
 
 // 27-cell traversal over the sorted atoms (offsets z-major, x fastest;
