@@ -173,6 +173,7 @@ enum { HDR_NTILES = 0, HDR_NCTILES = 1, HDR_SPLIT = 2, HDR_ORDER = 3 };
 // SPLIT: workgroups per cell tile in k_sort; ORDER: tile order of the step
 // kernel's workgroups (ORDER_PASSES or ORDER_SLABS, see TileWalk)
 enum { ORDER_PASSES = 0, ORDER_SLABS = 1 };
+constexpr size_t WALK_BYTES = 16 * 64 * 4;  // Tables::walk
 
 // Each replica has two descriptors (see SlotDev); CtlDev::var_ring says
 // which one holds a given state.
@@ -182,6 +183,10 @@ struct Tables {
   const int32_t *tile_rep;    // atom tile -> replica
   const int32_t *ctile_rep;   // cell tile -> replica
   int32_t *hdr;
+  // k_step's tile claims: walk[64 x] counts the tiles claimed by workgroup
+  // group x (x = block & 7), walk[64 (8 + x)] its workgroups that finished;
+  // zero between launches (the group's last workgroup resets both)
+  int32_t *walk;
   int32_t nslots;
 };
 

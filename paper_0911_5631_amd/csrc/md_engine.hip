@@ -201,6 +201,7 @@ struct Engine {
   SlotDev *d_slots = nullptr;   // [2 * max_slots]
   CtlDev *d_ctl = nullptr;
   int32_t *d_tile_rep = nullptr, *d_ctile_rep = nullptr, *d_hdr = nullptr;
+  int32_t *d_walk = nullptr;    // k_step's tile claims (Tables::walk)
   int tile_cap = 0, ctile_cap = 0;
   CtlDev *h_ctl = nullptr;      // pinned
   SlotDev *h_slots = nullptr;   // pinned [2 * max_slots]
@@ -239,6 +240,7 @@ struct Engine {
     t.tile_rep = d_tile_rep;
     t.ctile_rep = d_ctile_rep;
     t.hdr = d_hdr;
+    t.walk = d_walk;
     t.nslots = max_slots;
     return t;
   }
@@ -345,7 +347,8 @@ md_status engine_init(Engine *e, int max_slots, const md_allocator *a, void *str
   e->d_slots = (SlotDev *)e->dmalloc(sizeof(SlotDev) * 2 * max_slots);
   e->d_ctl = (CtlDev *)e->dmalloc(sizeof(CtlDev) * max_slots);
   e->d_hdr = (int32_t *)e->dmalloc(256);
-  if (!e->d_slots || !e->d_ctl || !e->d_hdr) return MD_ERR_OOM;
+  e->d_walk = (int32_t *)e->dmalloc(WALK_BYTES);
+  if (!e->d_slots || !e->d_ctl || !e->d_hdr || !e->d_walk) return MD_ERR_OOM;
   err = hipHostMalloc((void **)&e->h_ctl, sizeof(CtlDev) * max_slots, hipHostMallocDefault);
   if (err == hipSuccess)
     err = hipHostMalloc((void **)&e->h_slots, sizeof(SlotDev) * 2 * max_slots,
@@ -356,6 +359,7 @@ md_status engine_init(Engine *e, int max_slots, const md_allocator *a, void *str
   err = hipMemsetAsync(e->d_ctl, 0, sizeof(CtlDev) * max_slots, e->work);
   if (err == hipSuccess) err = hipMemsetAsync(e->d_slots, 0, sizeof(SlotDev) * 2 * max_slots, e->work);
   if (err == hipSuccess) err = hipMemsetAsync(e->d_hdr, 0, 256, e->work);
+  if (err == hipSuccess) err = hipMemsetAsync(e->d_walk, 0, WALK_BYTES, e->work);
   if (err == hipSuccess) err = hipStreamSynchronize(e->work);
   return err == hipSuccess ? MD_OK : e->fail("engine init", err);
 }
@@ -378,6 +382,7 @@ void engine_free(Engine *e) {
   e->dfree(e->d_slots);
   e->dfree(e->d_ctl);
   e->dfree(e->d_hdr);
+  e->dfree(e->d_walk);
   e->dfree(e->d_tile_rep);
   e->dfree(e->d_ctile_rep);
   if (e->h_ctl) (void)hipHostFree(e->h_ctl);

@@ -1320,9 +1320,12 @@ __device__ __forceinline__ bool unordered(SlotC &S, const Ctl &C, int64_t k, int
 // ACC: the steps of a block, which sum their properties and add them to the
 // block sums.  MIX: a mixture (species staged with the window, pair
 // parameters in LDS).
+// pub: thread TILE - 64 stores pubv there before the tile's last barrier
+// (the step kernel's next tile, published to the workgroup without a
+// barrier of its own).
 template <typename R, bool ACC, bool MIX>
 __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k, int mode, bool cells,
-                          bool build, bool last, bool bin_next) {
+                          bool build, bool last, bool bin_next, int *pub, int pubv) {
   const int i = lt * TILE + threadIdx.x;
   const bool act = i < S.n;
   const int pb = (int)(k & 1);
@@ -1608,6 +1611,7 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
       }
     }
   }
+  if (pub != nullptr && threadIdx.x == TILE - 64) *pub = pubv;
   __syncthreads();
 }
 
@@ -1626,8 +1630,45 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
   int64_t k = 0;
   bool skip = true, last = false, cells = false, build = false, bin_next = false;
   const TileWalk tw(blockIdx.x, gridDim.x, nt, cview(T.hdr)[HDR_ORDER]);
-  for (int t = tw.t; t < tw.end; t += tw.step) {
-    const int r = cview(T.tile_rep)[t];
+  // A launch with more tiles than workgroups takes them on demand; the
+  // others walk them statically.  On demand: workgroup group x = block & 7
+  // (the XCD the block is dispatched to) owns the tiles of the static
+  // walk's share of x (TileWalk); a workgroup does the first tile of its
+  // static walk, then claims the next ones from the group's counter, so one
+  // whose tiles ran long does fewer of them.  The claim for the next tile
+  // goes out from the last wave as a tile starts (that wave waits for the
+  // window build anyway, so the claim's latency hides) and is published to
+  // the workgroup before the tile's last barrier.  Every workgroup counts
+  // itself finished once a claim finds no tile left; the last of the group
+  // resets the group's counters for the next launch.
+  const bool dyn = (gridDim.x & 7) == 0 && nt > (int)gridDim.x;
+  const int x = blockIdx.x & 7, nwg = gridDim.x >> 3;
+  const bool slabs = cview(T.hdr)[HDR_ORDER] == ORDER_SLABS;
+  constexpr int CLAIMER = TILE - 64;
+  __shared__ int s_claim[2];
+  int32_t *cnt = T.walk + 64 * x, *fin = T.walk + 64 * (8 + x);
+  // the tile after this one: the static walk's, or the claimed one (double-
+  // buffered: a slot is written again only after the last barrier of the
+  // next tile, which every thread passes after reading it)
+  int it = 0, claim = 0;
+  bool stepped = false;
+  auto next = [&](int t) {
+    if (!dyn) return t + tw.step;
+    const int b = it & 1;
+    ++it;
+    if (!stepped) {
+      if (threadIdx.x == CLAIMER) s_claim[b] = claim;
+      __syncthreads();
+    }
+    const int q = nwg + s_claim[b];  // the q-th tile of group x in the walk's order
+    const int u = slabs ? tw.t - (int)(blockIdx.x >> 3) + q
+                        : x * nwg + q % nwg + (q / nwg) * (int)gridDim.x;
+    return u < tw.end ? u : nt;
+  };
+  for (int t = tw.t; t < tw.end; t = next(t)) {
+    stepped = false;
+    if (dyn && threadIdx.x == CLAIMER) claim = atomicAdd(cnt, 1);
+    const int r = T.nslots == 1 ? 0 : cview(T.tile_rep)[t];
     if (r != rc) {
       rc = r;
       skip = true;
@@ -1670,9 +1711,15 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
       C.var_ring[mod3(k)] = var;
       C.ord_ring[mod3(k)] = unordered(S, *cview(&C), k, mode) ? 1 : 0;
     }
-    step_tile<R, ACC, MIX>(S, C, lt, k, mode, cells, build, last, bin_next);
+    step_tile<R, ACC, MIX>(S, C, lt, k, mode, cells, build, last, bin_next,
+                           dyn ? &s_claim[it & 1] : nullptr, claim);
+    stepped = true;
     if (mode == MODE_STEP && lt == 0 && threadIdx.x < VSPREAD)
       S.vring[(mod3(k + 1) * VSPREAD + threadIdx.x) * 16] = 0ull;
+  }
+  if (dyn && threadIdx.x == CLAIMER && atomicAdd(fin, 1) == nwg - 1) {
+    atomicExch(cnt, 0);
+    atomicExch(fin, 0);
   }
 }
 
