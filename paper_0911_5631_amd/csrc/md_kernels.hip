@@ -1071,7 +1071,9 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   const double L = S.L, rn2 = S.rn2, rc2 = S.rc2;
   const R ushift = (R)S.ushift;
   const int mcap = S.mcap;
-  const auto Wc = gp(S.W) + i;
+  // the next list entry's address: row min(m, mcap - 1) of W (an atom whose
+  // list overflows keeps overwriting its last row; its list is not used)
+  auto wp = gp(S.W) + i;
   const size_t np = (size_t)S.npad;
   const auto CS = cview((const int32_t *)S.cs);  // written by the sort, read-only here
   const int cx = ci % G, cy = (ci / G) % G, cz = ci / (G * G);
@@ -1086,17 +1088,21 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   // without reordering, position j of cell order is the atom stored at perm[j]
   const bool noreo = unord;
   const gcint PERM = gp((const int32_t *)S.perm);
-  auto candidates = [&](auto from_lds, int lo, int hi, int delta, uint32_t code, double bx,
-                        double by, double bz) {
+  // SELF: the row holds atom i itself (the atom's own row, q = 4: the 27
+  // cells are distinct for G >= 3, so no other row does)
+  auto candidates = [&](auto from_lds, auto self, int lo, int hi, int delta, uint32_t code,
+                        double bx, double by, double bz) {
     // ALL_LDS also means that no lane of the wave applies an image shift
-    constexpr bool ALL_LDS = decltype(from_lds)::value;
+    constexpr bool ALL_LDS = decltype(from_lds)::value, SELF = decltype(self)::value;
     const bool lds = ALL_LDS || delta != NOSLOT;
     for (int j0 = lo; j0 < hi; j0 += 4) {
       double xj[4], yj[4], zj[4];
       int sj[4], js[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int j = min(j0 + u, hi - 1);
+        // from the window, a candidate past hi reads one of the (padded)
+        // slots after the range's last, and is not taken
+        const int j = ALL_LDS ? j0 + u : min(j0 + u, hi - 1);
         js[u] = j;
         if (ALL_LDS || lds) {
           xj[u] = sx[j + delta];
@@ -1114,7 +1120,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + u;
-        if (j >= hi || js[u] == i) continue;
+        if (j >= hi || (SELF && js[u] == i)) continue;
         double dx = xi - xj[u], dy = yi - yj[u], dz = zi - zj[u];
         if (!ALL_LDS) {
           dx = dx + bx;
@@ -1125,8 +1131,9 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
         if (s < rn2) {
           if (build) {
             const uint32_t idx = lds ? (uint32_t)(j + delta) : ((uint32_t)js[u] | GFLAG);
-            if (m < mcap) Wc[(size_t)m * np] = (int32_t)(idx | code);
+            *wp = (int32_t)(idx | code);
             ++m;
+            wp += m < mcap ? np : (size_t)0;
           }
           if (MIX) {
             const int kk = (spi * MAXSP + sj[u]) & (MAXSP * MAXSP - 1);
@@ -1138,11 +1145,14 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
       }
     }
   };
-  auto range = [&](int lo, int hi, int delta, uint32_t code, double bx, double by, double bz) {
-    if (__ballot(lo < hi && (delta == NOSLOT || code != 0)) == 0)
-      candidates(std::true_type{}, lo, hi, delta, code, bx, by, bz);
+  auto range = [&](bool own, int lo, int hi, int delta, uint32_t code, double bx, double by,
+                   double bz) {
+    if (__ballot(lo < hi && (delta == NOSLOT || code != 0)) != 0)
+      candidates(std::false_type{}, std::true_type{}, lo, hi, delta, code, bx, by, bz);
+    else if (own)
+      candidates(std::true_type{}, std::true_type{}, lo, hi, delta, code, bx, by, bz);
     else
-      candidates(std::false_type{}, lo, hi, delta, code, bx, by, bz);
+      candidates(std::true_type{}, std::false_type{}, lo, hi, delta, code, bx, by, bz);
   };
   // storage bounds of row q: the x-neighbours that do not wrap (one
   // contiguous range) and the one wrapped cell, visited first when cx == 0
@@ -1169,9 +1179,12 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   // Every candidate then takes its own window offset and x image shift.
   const bool edge = wlo || whi;
   const bool anyedge = __ballot(edge) != 0;
-  auto merged = [&](int loM, int hiM, int dM, int loW, int hiW, int dW, uint32_t cyz, double by,
-                    double bz) {
-    if (!edge) loW = hiW = 0;
+  // ALL_LDS: every piece of the row is in the window for every lane; YZ:
+  // some lane's row is a y or z image; SELF: the atom's own row
+  auto merged_t = [&](auto all_lds, auto yz, auto self, int loM, int hiM, int dM, int loW,
+                      int hiW, int dW, uint32_t cyz, double by, double bz) {
+    constexpr bool ALL_LDS = decltype(all_lds)::value, YZ = decltype(yz)::value,
+                   SELF = decltype(self)::value;
     const int loF = wlo ? loW : loM, hiF = wlo ? hiW : hiM;
     const int loS = wlo ? loM : loW, hiS = wlo ? hiM : hiW;
     const int lenF = hiF - loF, tot = lenF + (hiS - loS);
@@ -1190,7 +1203,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
         const int d = isw[u] ? dW : dM;
         jj[u] = j;
         js[u] = j;
-        if (d != NOSLOT) {
+        if (ALL_LDS || d != NOSLOT) {
           xj[u] = sx[j + d];
           yj[u] = sy[j + d];
           zj[u] = sz[j + d];
@@ -1205,18 +1218,22 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (k0 + u >= tot || js[u] == i) continue;
+        if (k0 + u >= tot || (SELF && js[u] == i)) continue;
         double dx = xi - xj[u], dy = yi - yj[u], dz = zi - zj[u];
         dx = dx + (isw[u] ? bw : 0.0);
-        dy = dy + by;
-        dz = dz + bz;
+        if (YZ) {
+          dy = dy + by;
+          dz = dz + bz;
+        }
         const double s = (dx * dx + dy * dy) + dz * dz;
         if (s < rn2) {
           if (build) {
             const int d = isw[u] ? dW : dM;
-            const uint32_t idx = d != NOSLOT ? (uint32_t)(jj[u] + d) : ((uint32_t)js[u] | GFLAG);
-            if (m < mcap) Wc[(size_t)m * np] = (int32_t)(idx | (isw[u] ? cw : cyz));
+            const uint32_t idx =
+                ALL_LDS || d != NOSLOT ? (uint32_t)(jj[u] + d) : ((uint32_t)js[u] | GFLAG);
+            *wp = (int32_t)(idx | (isw[u] ? cw : cyz));
             ++m;
+            wp += m < mcap ? np : (size_t)0;
           }
           if (MIX) {
             const int kk = (spi * MAXSP + sj[u]) & (MAXSP * MAXSP - 1);
@@ -1227,6 +1244,20 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
         }
       }
     }
+  };
+  // the usual row (interior, wholly in the window, not the atom's own) skips
+  // the per-candidate choice of window or global memory, the y/z image
+  // shifts (zero there: x + 0 == x) and the test for atom i itself
+  auto merged = [&](bool own, int loM, int hiM, int dM, int loW, int hiW, int dW, uint32_t cyz,
+                    double by, double bz) {
+    if (!edge) loW = hiW = 0;
+    const bool glob = (hiM > loM && dM == NOSLOT) || (hiW > loW && dW == NOSLOT);
+    if (own || __ballot(glob || by != 0.0 || bz != 0.0) != 0)
+      merged_t(std::false_type{}, std::true_type{}, std::true_type{}, loM, hiM, dM, loW, hiW, dW,
+               cyz, by, bz);
+    else
+      merged_t(std::true_type{}, std::false_type{}, std::false_type{}, loM, hiM, dM, loW, hiW,
+               dW, cyz, by, bz);
   };
   int cur[4], nxt[4];
   bounds(0, cur);
@@ -1248,9 +1279,9 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
       dg = w.dl[e + 2];
     }
     if (anyedge)
-      merged(cur[0], cur[1], dm, cur[2], cur[3], wlo ? dg : d0, cyz, by, bz);
+      merged(q == 4, cur[0], cur[1], dm, cur[2], cur[3], wlo ? dg : d0, cyz, by, bz);
     else
-      range(cur[0], cur[1], dm, cyz, 0.0, by, bz);
+      range(q == 4, cur[0], cur[1], dm, cyz, 0.0, by, bz);
 #pragma unroll
     for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
   }
@@ -1364,12 +1395,14 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
   }
 
   // the tile's LDS window: made with the list at a sort, read back otherwise
-  __shared__ double sx[WCAP], sy[WCAP], sz[WCAP];
+  // (4 slots of padding: a traversal group may read up to 3 slots past the
+  // window's last)
+  __shared__ double sx[WCAP + 4], sy[WCAP + 4], sz[WCAP + 4];
   __shared__ Window win;
   // a mixture: the window's species and the pair table (the barriers below
   // publish them)
   __shared__ typename std::conditional<MIX, PairTab, char>::type stab;
-  __shared__ int8_t ssp_store[MIX ? WCAP : 1];
+  __shared__ int8_t ssp_store[MIX ? WCAP + 4 : 1];
   const PairTab *tab = nullptr;
   int8_t *ssp = nullptr;
   const gcint SP = gp((const int32_t *)S.sp);
