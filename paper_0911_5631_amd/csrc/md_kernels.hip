@@ -1432,6 +1432,30 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
     if (threadIdx.x < WSTRIDE) win.wt[threadIdx.x] = wtv;
     __syncthreads();
   }
+  // The first NP entries that live outside the window: their coordinates
+  // are gathered now, while the window is staged, instead of inside the
+  // pair loop (by the waves that have such entries; only a group holding
+  // one reads them).
+  constexpr int NP = 8;  // (all NE = 12 of FP32 forces: more registers, spills)
+  double gx[NP], gy[NP], gz[NP];
+  int gs[NP];
+  uint32_t gor = 0;
+  if (list && act && m <= S.mcap)
+    for (int u = 0; u < NP; ++u) gor |= u < m ? e[u] : 0u;
+  if (__ballot((gor & GFLAG) != 0) != 0) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      gx[u] = gy[u] = gz[u] = 0.0;
+      gs[u] = 0;
+      if (u < m && (e[u] & GFLAG) && m <= S.mcap && act) {
+        const uint32_t idx = e[u] & IDX_MASK;
+        gx[u] = X[idx];
+        gy[u] = Y[idx];
+        gz[u] = Z[idx];
+        if (MIX) gs[u] = SP[idx];
+      }
+    }
+  }
   if (cells || list) {
     stage_window<MIX>(win.wt, X, Y, Z, sx, sy, sz, SP, ssp);
     __syncthreads();
@@ -1454,7 +1478,10 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
         // length takes the group with no effect, so the wave runs max(m)/4
         // groups whatever the spread of m.  A group without image codes
         // anywhere in the wave skips the shifts.
-        auto group = [&](int q0, uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
+        // PRE: entries q0 .. q0+3 are among the first NP (their global
+        // coordinates gathered above)
+        auto group = [&](auto pre, int q0, uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
+          constexpr bool PRE = decltype(pre)::value;
           const bool ok[4] = {q0 < m, q0 + 1 < m, q0 + 2 < m, q0 + 3 < m};
           const uint32_t eg[4] = {ok[0] ? e0 : 0u, ok[1] ? e1 : 0u, ok[2] ? e2 : 0u,
                                   ok[3] ? e3 : 0u};
@@ -1470,6 +1497,19 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
               yj[u] = sy[sl];
               zj[u] = sz[sl];
               if (MIX) sj[u] = ssp[sl];
+            }
+          } else if constexpr (PRE) {
+            // window slots from LDS (slot 0 for an entry outside it), the
+            // others from the gathered coordinates
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const bool g = (eg[u] & GFLAG) != 0;
+              const uint32_t sl = g ? 0u : eg[u] & IDX_MASK;
+              const int qu = min(q0 + u, NP - 1);
+              xj[u] = g ? gx[qu] : sx[sl];
+              yj[u] = g ? gy[qu] : sy[sl];
+              zj[u] = g ? gz[qu] : sz[sl];
+              if (MIX) sj[u] = g ? gs[qu] : ssp[sl];
             }
           } else {
 #pragma unroll
@@ -1489,14 +1529,18 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
           }
         };
 #pragma unroll
-        for (int g = 0; g < NE / 4; ++g)
+        for (int g = 0; g < NP / 4; ++g)
           if (__ballot(4 * g < m) != 0)
-            group(4 * g, e[4 * g], e[4 * g + 1], e[4 * g + 2], e[4 * g + 3]);
+            group(std::true_type{}, 4 * g, e[4 * g], e[4 * g + 1], e[4 * g + 2], e[4 * g + 3]);
+#pragma unroll
+        for (int g = NP / 4; g < NE / 4; ++g)
+          if (__ballot(4 * g < m) != 0)
+            group(std::false_type{}, 4 * g, e[4 * g], e[4 * g + 1], e[4 * g + 2], e[4 * g + 3]);
         for (int q = NE; __ballot(q < m) != 0; q += 4) {
           uint32_t ew[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) ew[u] = q + u < m ? (uint32_t)Wc[(size_t)(q + u) * np] : 0u;
-          group(q, ew[0], ew[1], ew[2], ew[3]);
+          group(std::false_type{}, q, ew[0], ew[1], ew[2], ew[3]);
         }
       } else {
         // the list overflowed its capacity at the last build: evaluate this
