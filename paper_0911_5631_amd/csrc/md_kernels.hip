@@ -1568,14 +1568,17 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
         for (int q = 0; q < 3; ++q) {
           v[q] = v[q] + S.hdt * f[q];  // (a) of step k+1
           xn[q] = xo[q] + S.dt * v[q];
-          gp(S.P[pb ^ 1][q])[i] = xn[q];
+          // streaming stores: the next step's kernels read these from
+          // any XCD, so they are not kept in this XCD's L2 (less for its
+          // write-back when the kernel ends)
+          __builtin_nontemporal_store(xn[q], &gp(S.P[pb ^ 1][q])[i]);
         }
         if (bin_next)
           bin_atom(S, C, (int)mod3(k + 1), i, xn[0], xn[1], xn[2], k + 1);
         else
           check_atom(S, C, xn[0], xn[1], xn[2], k + 1);
       }
-      for (int q = 0; q < 3; ++q) gp(S.V[pb ^ 1][q])[i] = v[q];
+      for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(v[q], &gp(S.V[pb ^ 1][q])[i]);
     }
     if (mode != MODE_STEP || last) {
       auto F = gp((R *)S.F);
