@@ -1368,7 +1368,10 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
   const double L = S.L;
 
   // loads that do not wait for the window: own position and velocity, list
-  // length and the first NE list entries (or the own cell when sorted)
+  // length and the first NE list entries (or the own cell when sorted).
+  // Velocities, list lengths and entries are read once a step: streaming
+  // (non-temporal) loads, so they do not displace the window data that
+  // neighbouring tiles read again from the caches.
   constexpr int NE = sizeof(R) == 8 ? 8 : 12;
   const bool list = !cells && force;
   const auto Wc = gp((const int32_t *)S.W) + i;
@@ -1384,11 +1387,12 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
     yi = Y[i];
     zi = Z[i];
     if (force)
-      for (int q = 0; q < 3; ++q) v[q] = gp(S.V[vb][q])[i];
+      for (int q = 0; q < 3; ++q) v[q] = __builtin_nontemporal_load(&gp(S.V[vb][q])[i]);
     if (list) {
-      m = gp(S.m)[i];
+      m = __builtin_nontemporal_load(&gp(S.m)[i]);
 #pragma unroll
-      for (int u = 0; u < NE; ++u) e[u] = u < S.mcap ? (uint32_t)Wc[(size_t)u * np] : 0u;
+      for (int u = 0; u < NE; ++u)
+        e[u] = u < S.mcap ? (uint32_t)__builtin_nontemporal_load(&Wc[(size_t)u * np]) : 0u;
     } else if (cells) {
       ci = gp(S.cell)[i];
     }
@@ -1539,7 +1543,8 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
         for (int q = NE; __ballot(q < m) != 0; q += 4) {
           uint32_t ew[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) ew[u] = q + u < m ? (uint32_t)Wc[(size_t)(q + u) * np] : 0u;
+          for (int u = 0; u < 4; ++u)
+            ew[u] = q + u < m ? (uint32_t)__builtin_nontemporal_load(&Wc[(size_t)(q + u) * np]) : 0u;
           group(std::false_type{}, q, ew[0], ew[1], ew[2], ew[3]);
         }
       } else {
