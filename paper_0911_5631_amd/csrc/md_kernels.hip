@@ -1369,9 +1369,11 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
 
   // loads that do not wait for the window: own position and velocity, list
   // length and the first NE list entries (or the own cell when sorted).
-  // Velocities, list lengths and entries are read once a step: streaming
-  // (non-temporal) loads, so they do not displace the window data that
-  // neighbouring tiles read again from the caches.
+  // Velocities, list lengths and these entries are read once a step:
+  // streaming (non-temporal) loads, so they do not displace the window data
+  // that neighbouring tiles read again from the caches.  (Entries past the
+  // first NE, the bulk of a long list such as LJ r_c = 3's, are read plainly:
+  // such lists stay in the last-level cache from step to step.)
   constexpr int NE = sizeof(R) == 8 ? 8 : 12;
   const bool list = !cells && force;
   const auto Wc = gp((const int32_t *)S.W) + i;
@@ -1543,8 +1545,7 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
         for (int q = NE; __ballot(q < m) != 0; q += 4) {
           uint32_t ew[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            ew[u] = q + u < m ? (uint32_t)__builtin_nontemporal_load(&Wc[(size_t)(q + u) * np]) : 0u;
+          for (int u = 0; u < 4; ++u) ew[u] = q + u < m ? (uint32_t)Wc[(size_t)(q + u) * np] : 0u;
           group(std::false_type{}, q, ew[0], ew[1], ew[2], ew[3]);
         }
       } else {
