@@ -829,18 +829,31 @@ __device__ void make_window(SlotC &S, int lt, Window &w, int *scratch) {
         xb = (sr == ns - 1 ? c_l % G : G - 1) + 1;
         ell = lane;
       }
-      for (int k = 2; k <= 64; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-          const int T2 = __shfl_xor(T, j, 64), a2 = __shfl_xor(xa, j, 64),
-                    b2 = __shfl_xor(xb, j, 64), l2 = __shfl_xor(ell, j, 64);
-          const bool up = (lane & k) == 0, lower = (lane & j) == 0;
-          if (lower == up ? T2 < T : T2 > T) {
-            T = T2;
-            xa = a2;
-            xb = b2;
-            ell = l2;
+      {
+        // sort the ns * 9 entries by row: each entry's rank is the number
+        // of entries before it (smaller row, or the same row and a lower
+        // lane), read lane by lane through scalar registers; the entries
+        // then move to their ranks through LDS (lanes without an entry keep
+        // theirs, past every rank)
+        const int ne9 = ns * 9;
+        int rank = lane;
+        if (lane < ne9) {
+          rank = 0;
+          for (int j = 0; j < ne9; ++j) {
+            const int Tj = __builtin_amdgcn_readlane(T, j);
+            rank += (Tj < T || (Tj == T && j < lane)) ? 1 : 0;
           }
         }
+        int *srt = scratch + 3 * 192;  // [4][64], after the pieces
+        srt[rank] = T;
+        srt[64 + rank] = xa;
+        srt[128 + rank] = xb;
+        srt[192 + rank] = ell;
+        T = srt[lane];
+        xa = srt[64 + lane];
+        xb = srt[128 + lane];
+        ell = srt[192 + lane];
+      }
       const int Tp = __shfl_up(T, 1, 64);
       const bool lead = T != INT_MAX && (lane == 0 || Tp != T);
       int ua = xa, ub = xb;
