@@ -316,46 +316,74 @@ __device__ __forceinline__ void visit_cell(SlotC &S, int set, int c, int cnt,
   }
 }
 
-// Maximum of the spread slots of ring entry e (each wave reads all slots).
+// Maximum of the spread slots of ring entry e (each wave reads all slots;
+// every lane loads, the upper half the same slots again, and those copies
+// count as zero: no lane-dependent branch for the loads to wait behind).  A
+// slot without a replica has no ring and reads as zero.
+static_assert((VSPREAD & (VSPREAD - 1)) == 0 && VSPREAD <= 64, "VSPREAD: a power of two");
 __device__ __forceinline__ double ring_max(SlotC &S, int64_t e) {
   const int l = threadIdx.x & 63;
   double v = 0.0;
-  if (l < VSPREAD) v = __longlong_as_double((long long)S.vring[(e * VSPREAD + l) * 16]);
-  return wave_max(v);
+  if (S.vring != nullptr)
+    v = __longlong_as_double((long long)S.vring[(e * VSPREAD + (l & (VSPREAD - 1))) * 16]);
+  return wave_max(l < VSPREAD ? v : 0.0);
+}
+
+// The same for all three ring entries at once: the loads do not wait for the
+// step number that selects an entry.  A slot without a replica has no ring
+// and reads as zero.
+__device__ __forceinline__ void ring_max3(SlotC &S, double (&v)[3]) {
+  const int l = threadIdx.x & 63;
+  double a[3] = {0.0, 0.0, 0.0};
+  if (l < VSPREAD && S.vring != nullptr)
+    for (int e = 0; e < 3; ++e)
+      a[e] = __longlong_as_double((long long)S.vring[(e * VSPREAD + l) * 16]);
+  for (int e = 0; e < 3; ++e) v[e] = wave_max(a[e]);
+}
+
+// Entry e (0, 1 or 2) of three values held in registers.
+template <class X>
+__device__ __forceinline__ X pick3(X a0, X a1, X a2, int64_t e) {
+  return e == 0 ? a0 : e == 1 ? a1 : a2;
 }
 
 // Whether r(k) is binned during step k-1, so that a sort at step k finds its
 // rows (binning every step would cost a step's worth of atomics and row
 // writes where a rebuild comes about one step in ten).  Always with the cell
 // method and at a forced rebuild; otherwise when the displacement rule of
-// rebuild_at, accumulated with BIN_AHEAD times the maximum speed of step
+// rebuild_rule, accumulated with BIN_AHEAD times the maximum speed of step
 // k-2 (that of step k-1 is not known while step k-1 runs), would fire at
 // step k.  The sort of step k evaluates the same expression from the same
 // committed words, so it knows whether the rows exist; when the rule fires
 // without them (the maximum speed grew by more than BIN_AHEAD in one step)
 // it latches ERR_UNBINNED and the host bins r(k) and resumes, so the
 // trajectory does not depend on the guess.  Called by whole waves.
+// bins_rule takes the words already read: D2 the committed displacement
+// after step k-2, V2 the maximum v^2 of step k-2.
+__device__ __forceinline__ bool bins_rule(const SlotC &S, int64_t force_step, int64_t k,
+                                          double D2, double V2) {
+  if (S.cell_only || k == force_step) return true;
+  const bool rb1 = (k - 1 == force_step) || D2 > S.half_shell;
+  const double D1 = (rb1 ? 0.0 : D2) + BIN_AHEAD * sqrt(V2) * S.dt;
+  return D1 > S.half_shell;
+}
 template <class Ctl>
 __device__ __forceinline__ bool bins_due(SlotC &S, const Ctl &C, int64_t k) {
   const double D2 = C.disp_ring[mod3(k - 2)];
   const double V2 = ring_max(S, mod3(k - 2));
-  if (S.cell_only || k == C.force_step) return true;
-  const bool rb1 = (k - 1 == C.force_step) || D2 > S.half_shell;
-  const double D1 = (rb1 ? 0.0 : D2) + BIN_AHEAD * sqrt(V2) * S.dt;
-  return D1 > S.half_shell;
+  return bins_rule(S, C.force_step, k, D2, V2);
 }
 
 // Rebuild decision for step k (Sec. 3.1): rebuilt when the accumulated sum
 // of vmax*dt exceeds delta/2.  disp after step k-1 is recomputed from the
-// committed disp after step k-2 and vmax of step k-1; *disp1 receives it.
-__device__ __forceinline__ bool rebuild_at(SlotC &S, const CtlDev &C, int64_t k,
-                                           double *disp1) {
-  const double D2 = C.disp_ring[mod3(k - 2)];
-  const double V1 = ring_max(S, mod3(k - 1));
-  const bool rb1 = (k - 1 == C.force_step) || D2 > S.half_shell;
+// committed disp after step k-2 (D2) and vmax^2 of step k-1 (V1); *disp1
+// receives it.
+__device__ __forceinline__ bool rebuild_rule(const SlotC &S, int64_t force_step, int64_t k,
+                                             double D2, double V1, double *disp1) {
+  const bool rb1 = (k - 1 == force_step) || D2 > S.half_shell;
   const double D1 = (rb1 ? 0.0 : D2) + sqrt(V1) * S.dt;
   *disp1 = D1;
-  return (k == C.force_step) || D1 > S.half_shell;
+  return (k == force_step) || D1 > S.half_shell;
 }
 
 // ---------------------------------------------------------------------------
@@ -424,11 +452,6 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
   __shared__ int s_wsum[4];
   __shared__ int s_bsum[4];
   __shared__ int s_bc[TILE], s_bb[TILE], s_bp[TILE];
-  const int nct = cview(T.hdr)[HDR_NCTILES];
-  // a cell tile is shared by nsp workgroups (dense systems, whose cells hold
-  // many atoms); unit u = (tile u / nsp, share u % nsp)
-  const int nsp = max(cview(T.hdr)[HDR_SPLIT], 1);
-  const int nunits = nct * nsp;
   // the decision for a replica is launch-invariant: a workgroup works it out
   // once for a run of consecutive cell tiles of one replica
   int rc = -1, var = 0;
@@ -437,42 +460,78 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
   double d1 = 0.0;
   // the atoms in a replica's tiles before tile run_upto (see below)
   int run_rep = -1, run_upto = 0, run_pre = 0;
-  for (int u = xcd_block(blockIdx.x, gridDim.x); u < nunits; u += gridDim.x) {
-    const int t = u / nsp, sp = u - t * nsp;
-    const int r = cview(T.ctile_rep)[t];
+  // one replica: every unit is replica 0's
+  const bool solo = T.nslots == 1;
+  // last reordering before step k (MODE_STEP)
+  int64_t reo1 = 0;
+  // works out the decision for replica r; leaves skip set when the launch
+  // has nothing to do for it
+  auto decide = [&](int r) {
     CtlDev &C = T.ctl[r];
     SlotC &S0 = slot(T, 2 * r);
-    if (r != rc) {
-      rc = r;
-      skip = true;
-      if (only >= 0 && r != only) continue;
-      if (mode == MODE_STEP) {
-        k = C.base + s + 1;
-        if (k > C.target) continue;
-        if (C.err != 0 && C.err_step <= k) continue;
-        var = C.var_ring[mod3(k - 1)];
-        rebuild = true;
-        d1 = 0.0;
-        if (!S0.cell_only) rebuild = rebuild_at(S0, C, k, &d1);
-        unbinned = rebuild && !bins_due(S0, C, k) && k != C.bins_step;
-        // reorder at this rebuild, or keep the storage order (Table 7: the
-        // reordering is done at the first rebuild N_R steps after the last)
-        reo = !S0.noreo && (S0.nr <= 0 || k - C.reo_ring[mod3(k - 1)] >= S0.nr);
-      } else {
-        if (!C.clean) continue;
-        k = C.done;
-        if (C.err != 0 && C.err_step <= k) continue;
-        var = C.var_ring[mod3(k)];
-        rebuild = true;
-        unbinned = false;
-        reo = !S0.noreo;  // a sort of the held state reorders (k_flip records it)
-      }
-      skip = false;
+    rc = r;
+    skip = true;
+    if (only >= 0 && r != only) return;
+    if (mode == MODE_STEP) {
+      // every word the rule reads is loaded before any is tested: an idle
+      // launch is this evaluation, and tested one after another the words
+      // were a chain of dependent loads
+      const int64_t base = C.base, target = C.target, err_step = C.err_step;
+      const int64_t force_step = C.force_step, bins_step = C.bins_step;
+      const int32_t err = C.err;
+      const int64_t ro0 = C.reo_ring[0], ro1 = C.reo_ring[1], ro2 = C.reo_ring[2];
+      const double dp0 = C.disp_ring[0], dp1 = C.disp_ring[1], dp2 = C.disp_ring[2];
+      const int32_t vr0 = C.var_ring[0], vr1 = C.var_ring[1], vr2 = C.var_ring[2];
+      double vm[3];
+      ring_max3(S0, vm);
+      k = base + s + 1;
+      const int64_t e1 = mod3(k - 1), e2 = mod3(k - 2);
+      const double D2 = pick3(dp0, dp1, dp2, e2);
+      var = pick3(vr0, vr1, vr2, e1);
+      reo1 = pick3(ro0, ro1, ro2, e1);
+      rebuild = true;
+      d1 = 0.0;
+      if (!S0.cell_only) rebuild = rebuild_rule(S0, force_step, k, D2, pick3(vm[0], vm[1], vm[2], e1), &d1);
+      unbinned = rebuild && !bins_rule(S0, force_step, k, D2, pick3(vm[0], vm[1], vm[2], e2)) &&
+                 k != bins_step;
+      // reorder at this rebuild, or keep the storage order (Table 7: the
+      // reordering is done at the first rebuild N_R steps after the last)
+      reo = !S0.noreo && (S0.nr <= 0 || k - reo1 >= S0.nr);
+      if (k > target || (err != 0 && err_step <= k)) return;
+    } else {
+      if (!C.clean) return;
+      k = C.done;
+      if (C.err != 0 && C.err_step <= k) return;
+      var = C.var_ring[mod3(k)];
+      rebuild = true;
+      unbinned = false;
+      reo = !S0.noreo;  // a sort of the held state reorders (k_flip records it)
     }
+    skip = false;
+  };
+  if (solo) {
+    // (needs no table read, so it overlaps the header's loads) with nothing
+    // to sort in this launch only the workgroup of unit 0 has work: it
+    // records the decision
+    decide(0);
+    if (skip || (mode == MODE_STEP && (!rebuild || unbinned) &&
+                 xcd_block(blockIdx.x, gridDim.x) != 0))
+      return;
+  }
+  const int nct = cview(T.hdr)[HDR_NCTILES];
+  // a cell tile is shared by nsp workgroups (dense systems, whose cells hold
+  // many atoms); unit u = (tile u / nsp, share u % nsp)
+  const int nsp = max(cview(T.hdr)[HDR_SPLIT], 1);
+  const int nunits = nct * nsp;
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < nunits; u += gridDim.x) {
+    const int t = u / nsp, sp = u - t * nsp;
+    const int r = solo ? 0 : cview(T.ctile_rep)[t];
+    CtlDev &C = T.ctl[r];
+    SlotC &S0 = slot(T, 2 * r);
+    if (r != rc) decide(r);
     // one replica: its units are all the launch has, so a workgroup with
     // nothing to do for it stops instead of visiting its other units (an
     // idle launch then costs one unit per workgroup)
-    const bool solo = T.nslots == 1;
     if (skip) {
       if (solo) break;
       continue;
@@ -487,7 +546,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
           latch_error(C, ERR_UNBINNED, k);
         } else {
           C.rb_ring[mod3(k)] = rebuild ? (reo ? RB_REORDER : RB_PERM) : RB_NONE;
-          C.reo_ring[mod3(k)] = rebuild && reo ? k : C.reo_ring[mod3(k - 1)];
+          C.reo_ring[mod3(k)] = rebuild && reo ? k : reo1;
           if (!S0.cell_only) {
             C.disp_ring[mod3(k - 1)] = d1;
             if (rebuild && k != C.force_step) C.n_rebuilds += 1;
@@ -1060,6 +1119,23 @@ __device__ __forceinline__ void stage_window(const int *wt, gcdouble X, gcdouble
   }
 }
 
+// Storage bounds of neighbour row q (dz = q / 3 - 1, dy = q % 3 - 1) of an
+// atom in cell (cx, cy, cz): the x-neighbours that do not wrap (one
+// contiguous range, b[0] .. b[1]) and the one wrapped cell (b[2] .. b[3]).
+template <class CSP>
+__device__ __forceinline__ void row_bounds(CSP CS, int G, int cx, int cy, int cz, int q,
+                                           int (&b)[4]) {
+  const int xm0 = max(cx - 1, 0), xm1 = min(cx + 2, G);
+  const int xe = cx == 0 ? G - 1 : 0;
+  const int nz = cz + q / 3 - 1, ny = cy + q % 3 - 1;
+  const int row = ((nz < 0 ? nz + G : nz >= G ? nz - G : nz) * G +
+                   (ny < 0 ? ny + G : ny >= G ? ny - G : ny)) * G;
+  b[0] = CS[row + xm0];
+  b[1] = CS[row + xm1];
+  b[2] = CS[row + xe];
+  b[3] = CS[row + xe + 1];
+}
+
 // 27-cell traversal over the sorted atoms (offsets z-major, x fastest;
 // ascending storage index within a cell, which is ascending index before the
 // sort).  The three cells of an x-row are one contiguous range of storage
@@ -1079,7 +1155,8 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
                                                double zi, bool build, bool force, bool energy,
                                                Acc<R> &a, const int8_t *ssp, gcint SP, int spi,
                                                const PairTab *tab, bool unord,
-                                               bool global_only = false) {
+                                               bool global_only = false,
+                                               const int *pre0 = nullptr) {
   const int G = S.G;
   const double L = S.L, rn2 = S.rn2, rc2 = S.rc2;
   const R ushift = (R)S.ushift;
@@ -1175,15 +1252,7 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
   const int xm0 = max(cx - 1, 0), xm1 = min(cx + 2, G);
   const int xe = cx == 0 ? G - 1 : 0;
   const bool wlo = cx == 0, whi = cx == G - 1 && cx != 0;
-  auto bounds = [&](int q, int (&b)[4]) {
-    const int nz = cz + q / 3 - 1, ny = cy + q % 3 - 1;
-    const int row = ((nz < 0 ? nz + G : nz >= G ? nz - G : nz) * G +
-                     (ny < 0 ? ny + G : ny >= G ? ny - G : ny)) * G;
-    b[0] = CS[row + xm0];
-    b[1] = CS[row + xm1];
-    b[2] = CS[row + xe];
-    b[3] = CS[row + xe + 1];
-  };
+  auto bounds = [&](int q, int (&b)[4]) { row_bounds(CS, G, cx, cy, cz, q, b); };
   // A wave with lanes at an x-edge of the box (cx = 0 or G-1) visits each
   // row as one loop over the lane's two ranges, the wrapped cell and the
   // row's own cells in x order (cell G-1 first when cx = 0, cell 0 last
@@ -1272,8 +1341,14 @@ __device__ __forceinline__ int traverse_sorted(SlotC &S, int i, int ci, gcdouble
       merged_t(std::true_type{}, std::false_type{}, std::false_type{}, loM, hiM, dM, loW, hiW,
                dW, cyz, by, bz);
   };
+  // (row 0's bounds may have been loaded by the caller, ahead of the window)
   int cur[4], nxt[4];
-  bounds(0, cur);
+  if (pre0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cur[u] = pre0[u];
+  } else {
+    bounds(0, cur);
+  }
 #pragma unroll 1
   for (int q = 0; q < 9; ++q) {
     if (q < 8) bounds(q + 1, nxt);
@@ -1434,6 +1509,13 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
       ((double *)&stab)[threadIdx.x] = gp((const double *)S.tab)[threadIdx.x];
     if (act) spi = SP[i];
   }
+  // a cell step: the bounds of the first neighbour row of the traversal go
+  // out before the window is built (wave 0 builds it; the others wait)
+  int b0[4] = {0, 0, 0, 0};
+  if (cells && act) {
+    const int G = S.G;
+    row_bounds(cview((const int32_t *)S.cs), G, ci % G, (ci / G) % G, ci / (G * G), 0, b0);
+  }
   if (cells && unordered(S, *cview(&C), k, mode)) {
     // no reordering: the tile's atoms are not a run of cells, so there is no
     // window; candidates are read from global memory through perm, and the
@@ -1485,7 +1567,7 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
     if (cells) {
       m = traverse_sorted<R, MIX>(S, i, ci, X, Y, Z, win, sx, sy, sz, xi, yi, zi, build, force,
                                   mode != MODE_STEP || last || ACC, a, ssp, SP, spi, tab,
-                                  unordered(S, *cview(&C), k, mode));
+                                  unordered(S, *cview(&C), k, mode), false, b0);
       if (build) gp(S.m)[i] = m;
     } else if (list) {
       if (m <= S.mcap) {
@@ -1720,7 +1802,6 @@ __device__ __forceinline__ void step_tile(SlotC &S, CtlDev &C, int lt, int64_t k
 template <typename R, bool ACC, bool MIX>
 __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int mode,
                                                           int force_build, int only) {
-  const int nt = cview(T.hdr)[HDR_NTILES];
   // what a workgroup decides per replica is launch-invariant: it is worked
   // out once for a run of consecutive tiles of one replica (every tile, for
   // a single system).  The control words read here are written by earlier
@@ -1728,7 +1809,83 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
   int rc = -1, var = 0;
   int64_t k = 0;
   bool skip = true, last = false, cells = false, build = false, bin_next = false;
-  const TileWalk tw(blockIdx.x, gridDim.x, nt, cview(T.hdr)[HDR_ORDER]);
+  // the header's words, lane l holding word l % 8: a vector load that goes
+  // out with the decision's loads and is waited for only where the tile
+  // loop needs it
+  const int hdr_l = cview(T.hdr)[threadIdx.x & 7];
+  // works out the decision for replica r; leaves skip set when the launch
+  // has nothing to do for it
+  auto decide = [&](int r) {
+    rc = r;
+    skip = true;
+    SlotC &S0 = slot(T, 2 * r);
+    auto &C = *cview(T.ctl + r);
+    if (only >= 0 && r != only) return;
+    last = false;
+    if (mode == MODE_STEP) {
+      // every word is read before any is tested: one round of loads where
+      // tests one after another made a chain of them
+      const int64_t base = C.base, target = C.target, err_step = C.err_step;
+      const int64_t force_step = C.force_step;
+      const int32_t err = C.err, fp64 = S0.fp64, cell_only = S0.cell_only;
+      const int32_t vr0 = C.var_ring[0], vr1 = C.var_ring[1], vr2 = C.var_ring[2];
+      const int32_t rb0 = C.rb_ring[0], rb1 = C.rb_ring[1], rb2 = C.rb_ring[2];
+      const double dp0 = C.disp_ring[0], dp1 = C.disp_ring[1], dp2 = C.disp_ring[2];
+      const unsigned long long *vring = S0.vring;
+      const double half_shell = S0.half_shell, dt = S0.dt;
+      // (the empty asm takes these words at one point: left to itself the
+      // compiler issued the descriptor's loads only after waiting for the
+      // control words, and the rule's only after the speed reduction)
+      asm volatile("" ::"s"(base), "s"(vring), "s"(fp64), "s"(cell_only), "s"(dp0), "s"(dp1),
+                   "s"(dp2), "s"(half_shell), "s"(dt));
+      k = base + s + 1;
+      const int64_t e0 = mod3(k), e1 = mod3(k - 1);
+      const double V1 = ring_max(S0, e1);
+      last = k == target;
+      var = pick3(vr0, vr1, vr2, e1);
+      // k_sort of this step decided, and if so gathered r(k) into the other
+      // variant (or, without reordering, found the cell order in place)
+      const int rb = pick3(rb0, rb1, rb2, e0);
+      cells = rb != RB_NONE;
+      build = cells && !cell_only;
+      if (rb == RB_REORDER) var ^= 1;
+      // r(k+1) is binned here if a sort at step k+1 may need its rows
+      bin_next = !last && bins_rule(S0, force_step, k + 1, pick3(dp0, dp1, dp2, e1), V1);
+      // stop at an error of an earlier step; one latched by this launch
+      // (while binning r(k+1), err_step = k + 1) must not stop the others
+      skip = fp64 != (sizeof(R) == 8) || k > target || (err != 0 && err_step <= k);
+    } else {
+      if (S0.fp64 != (sizeof(R) == 8) || !C.clean) return;
+      k = C.done;
+      var = C.var_ring[mod3(k)];
+      build = !S0.cell_only && (force_build || mode == MODE_BUILD);
+      cells = build || S0.cell_only;
+      skip = C.err != 0 && C.err_step <= k;
+    }
+  };
+  const int x = blockIdx.x & 7, nwg = gridDim.x >> 3;
+  constexpr int CLAIMER = TILE - 64;
+  int32_t *cnt = T.walk + 64 * x, *fin = T.walk + 64 * (8 + x);
+  // one replica: decided before the tile loop (the decision needs no tile
+  // table, so its loads go out with the header's); a launch with nothing to
+  // step for it ends here, counting every workgroup finished if it takes
+  // its tiles on demand (below)
+  const bool solo = T.nslots == 1;
+  if (solo) {
+    decide(0);
+    if (skip) {
+      const int nt = __builtin_amdgcn_readlane(hdr_l, HDR_NTILES);
+      if ((gridDim.x & 7) == 0 && nt > (int)gridDim.x && threadIdx.x == CLAIMER &&
+          atomicAdd(fin, 1) == nwg - 1) {
+        atomicExch(cnt, 0);
+        atomicExch(fin, 0);
+      }
+      return;
+    }
+  }
+  const int nt = __builtin_amdgcn_readlane(hdr_l, HDR_NTILES);
+  const int order = __builtin_amdgcn_readlane(hdr_l, HDR_ORDER);
+  const TileWalk tw(blockIdx.x, gridDim.x, nt, order);
   // A launch with more tiles than workgroups takes them on demand; the
   // others walk them statically.  On demand: workgroup group x = block & 7
   // (the XCD the block is dispatched to) owns the tiles of the static
@@ -1741,11 +1898,8 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
   // itself finished once a claim finds no tile left; the last of the group
   // resets the group's counters for the next launch.
   const bool dyn = (gridDim.x & 7) == 0 && nt > (int)gridDim.x;
-  const int x = blockIdx.x & 7, nwg = gridDim.x >> 3;
-  const bool slabs = cview(T.hdr)[HDR_ORDER] == ORDER_SLABS;
-  constexpr int CLAIMER = TILE - 64;
+  const bool slabs = order == ORDER_SLABS;
   __shared__ int s_claim[2];
-  int32_t *cnt = T.walk + 64 * x, *fin = T.walk + 64 * (8 + x);
   // the tile after this one: the static walk's, or the claimed one (double-
   // buffered: a slot is written again only after the last barrier of the
   // next tile, which every thread passes after reading it)
@@ -1767,39 +1921,8 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
   for (int t = tw.t; t < tw.end; t = next(t)) {
     stepped = false;
     if (dyn && threadIdx.x == CLAIMER) claim = atomicAdd(cnt, 1);
-    const int r = T.nslots == 1 ? 0 : cview(T.tile_rep)[t];
-    if (r != rc) {
-      rc = r;
-      skip = true;
-      SlotC &S0 = slot(T, 2 * r);
-      auto &C = *cview(T.ctl + r);
-      if ((only >= 0 && r != only) || S0.fp64 != (sizeof(R) == 8)) continue;
-      last = false;
-      if (mode == MODE_STEP) {
-        k = C.base + s + 1;
-        if (k > C.target) continue;
-        last = k == C.target;
-        var = C.var_ring[mod3(k - 1)];
-        // k_sort of this step decided, and if so gathered r(k) into the other
-        // variant (or, without reordering, found the cell order in place)
-        const int rb = C.rb_ring[mod3(k)];
-        cells = rb != RB_NONE;
-        build = cells && !S0.cell_only;
-        if (rb == RB_REORDER) var ^= 1;
-        // r(k+1) is binned here if a sort at step k+1 may need its rows
-        bin_next = !last && bins_due(S0, C, k + 1);
-      } else {
-        if (!C.clean) continue;
-        k = C.done;
-        var = C.var_ring[mod3(k)];
-        build = !S0.cell_only && (force_build || mode == MODE_BUILD);
-        cells = build || S0.cell_only;
-      }
-      // stop at an error of an earlier step; one latched by this launch
-      // (while binning r(k+1), err_step = k + 1) must not stop the others
-      if (C.err != 0 && C.err_step <= k) continue;
-      skip = false;
-    }
+    const int r = solo ? 0 : cview(T.tile_rep)[t];
+    if (r != rc) decide(r);
     if (skip) continue;
     CtlDev &C = T.ctl[r];
     SlotC &S = slot(T, 2 * r + var);
