@@ -157,6 +157,7 @@ struct CtlDev {
                        // RB_REORDER into the other variant, RB_PERM in place
   int32_t ord_ring[3]; // 1 if the storage of state k is not the cell order of the last
                        // sort (it rebuilt without reordering since), slot k % 3
+  int32_t bin_ring[3]; // 1 if step k bins r(k+1) (decided by k_sort of step k), slot k % 3
   int32_t err;         // latched ERR_* bits
   int32_t max_h;       // largest cell occupancy seen by a sort
   int32_t pad1;

@@ -462,8 +462,9 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
   int run_rep = -1, run_upto = 0, run_pre = 0;
   // one replica: every unit is replica 0's
   const bool solo = T.nslots == 1;
-  // last reordering before step k (MODE_STEP)
+  // last reordering before step k, and whether step k bins r(k+1) (MODE_STEP)
   int64_t reo1 = 0;
+  bool bin1 = false;
   // works out the decision for replica r; leaves skip set when the launch
   // has nothing to do for it
   auto decide = [&](int r) {
@@ -491,9 +492,14 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
       reo1 = pick3(ro0, ro1, ro2, e1);
       rebuild = true;
       d1 = 0.0;
-      if (!S0.cell_only) rebuild = rebuild_rule(S0, force_step, k, D2, pick3(vm[0], vm[1], vm[2], e1), &d1);
+      const double V1 = pick3(vm[0], vm[1], vm[2], e1);
+      if (!S0.cell_only) rebuild = rebuild_rule(S0, force_step, k, D2, V1, &d1);
       unbinned = rebuild && !bins_rule(S0, force_step, k, D2, pick3(vm[0], vm[1], vm[2], e2)) &&
                  k != bins_step;
+      // the step kernel's binning ahead for step k + 1 (see bins_due): the
+      // rule of step k + 1 from the displacement after step k-1 (d1, which
+      // this launch commits) and the maximum speed of step k-1
+      bin1 = k != target && bins_rule(S0, force_step, k + 1, d1, V1);
       // reorder at this rebuild, or keep the storage order (Table 7: the
       // reordering is done at the first rebuild N_R steps after the last)
       reo = !S0.noreo && (S0.nr <= 0 || k - reo1 >= S0.nr);
@@ -546,6 +552,7 @@ __global__ __launch_bounds__(TILE) void k_sort(Tables T, int s, int mode, int on
           latch_error(C, ERR_UNBINNED, k);
         } else {
           C.rb_ring[mod3(k)] = rebuild ? (reo ? RB_REORDER : RB_PERM) : RB_NONE;
+          C.bin_ring[mod3(k)] = bin1 ? 1 : 0;
           C.reo_ring[mod3(k)] = rebuild && reo ? k : reo1;
           if (!S0.cell_only) {
             C.disp_ring[mod3(k - 1)] = d1;
@@ -1826,21 +1833,16 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
       // every word is read before any is tested: one round of loads where
       // tests one after another made a chain of them
       const int64_t base = C.base, target = C.target, err_step = C.err_step;
-      const int64_t force_step = C.force_step;
       const int32_t err = C.err, fp64 = S0.fp64, cell_only = S0.cell_only;
       const int32_t vr0 = C.var_ring[0], vr1 = C.var_ring[1], vr2 = C.var_ring[2];
       const int32_t rb0 = C.rb_ring[0], rb1 = C.rb_ring[1], rb2 = C.rb_ring[2];
-      const double dp0 = C.disp_ring[0], dp1 = C.disp_ring[1], dp2 = C.disp_ring[2];
-      const unsigned long long *vring = S0.vring;
-      const double half_shell = S0.half_shell, dt = S0.dt;
+      const int32_t bn0 = C.bin_ring[0], bn1 = C.bin_ring[1], bn2 = C.bin_ring[2];
       // (the empty asm takes these words at one point: left to itself the
       // compiler issued the descriptor's loads only after waiting for the
-      // control words, and the rule's only after the speed reduction)
-      asm volatile("" ::"s"(base), "s"(vring), "s"(fp64), "s"(cell_only), "s"(dp0), "s"(dp1),
-                   "s"(dp2), "s"(half_shell), "s"(dt));
+      // control words)
+      asm volatile("" ::"s"(base), "s"(fp64), "s"(cell_only));
       k = base + s + 1;
       const int64_t e0 = mod3(k), e1 = mod3(k - 1);
-      const double V1 = ring_max(S0, e1);
       last = k == target;
       var = pick3(vr0, vr1, vr2, e1);
       // k_sort of this step decided, and if so gathered r(k) into the other
@@ -1849,8 +1851,9 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
       cells = rb != RB_NONE;
       build = cells && !cell_only;
       if (rb == RB_REORDER) var ^= 1;
-      // r(k+1) is binned here if a sort at step k+1 may need its rows
-      bin_next = !last && bins_rule(S0, force_step, k + 1, pick3(dp0, dp1, dp2, e1), V1);
+      // r(k+1) is binned here if a sort at step k+1 may need its rows (the
+      // rule of bins_due, evaluated by k_sort of this step)
+      bin_next = pick3(bn0, bn1, bn2, e0) != 0;
       // stop at an error of an earlier step; one latched by this launch
       // (while binning r(k+1), err_step = k + 1) must not stop the others
       skip = fp64 != (sizeof(R) == 8) || k > target || (err != 0 && err_step <= k);
