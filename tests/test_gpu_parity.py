@@ -528,3 +528,31 @@ def test_rebuild_the_step_before_did_not_bin_for(precision, tol):
     b.close()
     assert bstep == 40 and bpr["n_late_bins"] == pr["n_late_bins"]
     assert np.array_equal(bp, p) and np.array_equal(bv, v)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_binning_ahead_covers_every_rebuild_of_a_fluid(precision):
+    """Sec. 3.1's rule rebuilds when the accumulated max-speed displacement
+    passes delta/2; positions are binned one step ahead when the same rule,
+    with 1.5 times the last maximum speed, could fire at the next step (the
+    sort kernel takes that decision for the step kernel).  In an ordinary
+    fluid the maximum speed never grows 1.5-fold in one step, so every
+    rebuild must find its rows binned ahead: no late binning, and the
+    rebuild steps and the final state equal the oracle's."""
+    pos, L = I.fcc_lattice(8, 0.8)                      # 2 048 atoms
+    pos = I.jitter(pos, L, 0.05, 91)
+    vel = I.random_velocities(len(pos), 1.0, 92)
+    n, steps = len(pos), 300
+    s = _system(pos, vel, L, shell=0.3, precision=precision)
+    sim = O.Sim(pos, vel, L, shell=0.3)
+    s.step(steps)
+    tr = sim.run(steps)
+    pr = s.props()
+    p, _, _, step = s.get_state()
+    rp, _, _, _ = sim.state()
+    sim.close()
+    s.close()
+    assert step == steps and pr["n_late_bins"] == 0
+    assert pr["n_rebuilds"] == int(tr[:, 5].sum()) >= 10
+    tol = 1e-9 if precision == "fp64" else 1e-5
+    assert np.abs(min_image(p - rp, L)).max() < tol
