@@ -353,8 +353,10 @@ __device__ __forceinline__ X pick3(X a0, X a1, X a2, int64_t e) {
 // method and at a forced rebuild; otherwise when the displacement rule of
 // rebuild_rule, accumulated with BIN_AHEAD times the maximum speed of step
 // k-2 (that of step k-1 is not known while step k-1 runs), would fire at
-// step k.  The sort of step k evaluates the same expression from the same
-// committed words, so it knows whether the rows exist; when the rule fires
+// step k.  The sort of step k-1, which holds every input of the rule, takes
+// this decision for the step kernel of step k-1 (CtlDev::bin_ring); the sort
+// of step k evaluates the same expression from the same committed words, so
+// it knows whether the rows exist; when the rule fires
 // without them (the maximum speed grew by more than BIN_AHEAD in one step)
 // it latches ERR_UNBINNED and the host bins r(k) and resumes, so the
 // trajectory does not depend on the guess.  Called by whole waves.
@@ -1811,8 +1813,9 @@ __global__ __launch_bounds__(TILE, MIX ? 3 : 4) void k_step(Tables T, int s, int
                                                           int force_build, int only) {
   // what a workgroup decides per replica is launch-invariant: it is worked
   // out once for a run of consecutive tiles of one replica (every tile, for
-  // a single system).  The control words read here are written by earlier
-  // launches only (this launch writes other ring slots and err_step > k).
+  // a single system).  The control words used here are written by earlier
+  // launches only (this launch writes other ring slots, read alongside but
+  // not used, and err_step > k).
   int rc = -1, var = 0;
   int64_t k = 0;
   bool skip = true, last = false, cells = false, build = false, bin_next = false;
