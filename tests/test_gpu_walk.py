@@ -89,3 +89,31 @@ def test_claimed_tiles_in_a_batch_match_solo_runs():
             gp, gv, gstep = out[k]
             assert gstep == step == s.steps
             assert np.array_equal(gp, p) and np.array_equal(gv, v), (order, k)
+
+
+def test_claimed_tiles_after_a_replay_cut_short():
+    """A step whose rule fires without binned rows (a late binning) stops the
+    rest of its replay: every workgroup skips those steps at once, which must
+    still leave the claim counters reset for the launches after the host has
+    binned the positions and resumed.  A lattice nearly at rest with one
+    pair pushed to r = 0.9 and a shell of 0.004 (the maximum speed jumps
+    from ~0.01 to ~0.7 in one step): same late binnings and bit-identical
+    state as the fixed walk, for both tile orders."""
+    pos, L = I.sc_lattice(16, 0.5)       # 4 096 atoms: 16 tiles
+    rng = np.random.Generator(np.random.PCG64(61))
+    vel = rng.uniform(-0.005, 0.005, pos.shape)
+    vel -= vel.mean(0)
+    d = pos[1] - pos[0]
+    d -= L * np.round(d / L)
+    pos[0] = pos[1] - d / np.linalg.norm(d) * 0.9
+    nt = -(-len(pos) // 256)
+    calls = (40, 24)
+    ref = _run(pos, vel, L, "fp32", calls, shell=0.004, grid=64, tile_order=SLABS)
+    assert ref[4]["grid"] >= nt and ref[3]["n_late_bins"] >= 1
+    for order in (PASSES, SLABS):
+        p, v, step, pr, used = _run(pos, vel, L, "fp32", calls, shell=0.004, grid=8,
+                                    tile_order=order)
+        assert used["grid"] == 8 < nt
+        assert step == ref[2] == sum(calls)
+        assert pr["n_late_bins"] == ref[3]["n_late_bins"]
+        assert np.array_equal(p, ref[0]) and np.array_equal(v, ref[1]), order
