@@ -573,7 +573,10 @@ md_status upload_tables(Engine *e) {
     // as many step-kernel workgroups as the chip holds at once (four per
     // CU), each walking its XCD's slab of tiles
     e->grid = std::max(1, std::min(nt, e->resident));
-    e->cgrid = std::max(1, std::min(nct * split, SORT_GRID));
+    // the sort: one unit per workgroup up to SORT_GRID, rounded up to a
+    // multiple of 8 so that runs of consecutive units share an XCD (see
+    // xcd_block; the few workgroups past the last unit find none)
+    e->cgrid = std::max(1, std::min((nct * split + 7) / 8 * 8, SORT_GRID));
   }
   if (e->grid_req > 0) e->grid = e->grid_req;
   if (e->cgrid_req > 0) e->cgrid = e->cgrid_req;
